@@ -1,0 +1,190 @@
+"""Throughput of the split-step semi-Lagrangian Vlasov-Poisson hot path.
+
+One step = one Strang step of the SLDG solver (degree 2) plus one Strang step
+of the cubic-spline solver on the same grid, each with its density, Poisson
+solve and per-step diagnostics (electric energy, mass, L1, L2, kinetic
+energy).  Every step performs 12 one-dimensional advection sweeps over the
+whole 4D array.  The workload is nonlinear Landau damping on 32^4 cells of
+degree 2 (96^4 dofs), FP64, dt = 0.05, synthetic initial data generated on
+the device.
+
+Prints one JSON line: value = dof-updates per second over the whole timed
+region (12 * 96^4 per step / time per step), the roofline of the dominant
+sweep kernel (timed with HIP events on the launch stream) and the CPU
+oracle's rate on a bounded sample.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SWEEPS_PER_STEP = 6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="landau_32")
+    ap.add_argument("--dtype", default=None, help="f64 or f32 (default: the config's)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--methods", default="sldg,spline")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, dtype):
+    """The oracle's sweep rate on a bounded sample: one SLDG and one spline
+    sweep along every axis of the full grid, shifts of the step's shape."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import sldg, spline
+    from vp_inputs import random_field
+
+    dims = w.dofs
+    rng = np.random.default_rng(0)
+    f = random_field(dims, seed=1, positive=True)
+    if dtype == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    updates = 0
+    t0 = time.perf_counter()
+    with threadpool_limits(limits=1):
+        for axis in range(4):
+            shape = [1, 1, 1, 1]
+            if axis < 2:
+                shape[axis + 2] = dims[axis + 2]
+            else:
+                shape[0], shape[1] = dims[0], dims[1]
+            sig = rng.uniform(-1.2, 1.2, size=shape)
+            sldg.sweep(f, axis, sig, w.degree)
+            spline.sweep(f, axis, sig)
+            updates += 2 * int(np.prod(dims))
+    dt = time.perf_counter() - t0
+    return {"value": updates / dt, "unit": "dof-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"one SLDG (degree {w.degree}) and one cubic-spline sweep along "
+                      f"each of the 4 axes of the full {'x'.join(map(str, dims))} grid, "
+                      f"float64, 1 thread, {dt:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the "
+              "multi-GPU sharding is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1803_02143_amd as vp
+    from vp_inputs import workload
+
+    w = workload(a.config)
+    dt = a.dtype or w.dtype
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    esize = 8 if dt == "f64" else 4
+    dims = w.dofs
+    n4 = int(np.prod(dims))
+    methods = [m for m in a.methods.split(",") if m]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    runs = []
+    for m in methods:
+        method = vp.METHOD_SLDG if m == "sldg" else vp.METHOD_SPLINE
+        deg = w.degree if m == "sldg" else -1
+        st = vp.VPState(method, w.degree, tdt, dims, w.lo, w.length)
+        f = torch.empty(dims, dtype=tdt, device="cuda")
+        tmp = torch.empty_like(f)
+        vp.vp_init(vp.IC_LANDAU if w.ic == "landau" else vp.IC_TWO_STREAM_SUM,
+                   w.eps, w.k, w.v0, deg, f, w.lo, w.length)
+        runs.append({"name": m, "st": st, "f": f, "tmp": tmp})
+
+    # warm-up, then the timed region: each solver advances `steps` Strang
+    # steps in one call, recording W and the moments of every state
+    for r in runs:
+        if a.warmup:
+            r["st"].step(r["f"], r["tmp"], a.warmup, w.dt, None, None, stream)
+        r["W"] = torch.empty(a.steps + 1, dtype=torch.float64, device="cuda")
+        r["mom"] = torch.empty(4 * (a.steps + 1), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    for r in runs:
+        r["st"].timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in runs:
+        r["st"].step(r["f"], r["tmp"], a.steps, w.dt, r["W"], r["mom"], stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for r in runs:
+        r["timers"] = r["st"].timing_read()
+        r["st"].timing_enable(False)
+
+    sweeps = SWEEPS_PER_STEP * len(runs)
+    value = sweeps * n4 * a.steps / elapsed
+    # per-kernel averages from the HIP events
+    detail = {}
+    dominant = None
+    for r in runs:
+        for name, (ms, cnt) in r["timers"].items():
+            if cnt == 0:
+                continue
+            key = f"{r['name']}_{name}"
+            avg = ms / cnt
+            d = {"avg_ms": avg, "launches": cnt, "total_ms": ms}
+            if name.startswith("sweep"):
+                d["dof_updates_per_s"] = n4 / (avg * 1e-3)
+                d["alg_GBs"] = 2.0 * n4 * esize / (avg * 1e-3) / 1e9
+            detail[key] = d
+            if name.startswith("sweep") and (dominant is None or ms > detail[dominant]["total_ms"]):
+                dominant = key
+    dom = detail[dominant]
+    roofline = {"kernel": dominant, "bound": "hbm", "achieved": dom["alg_GBs"],
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["alg_GBs"] / HBM_PEAK_GBS,
+                "traffic": None,
+                "alg_bytes_per_launch": 2 * n4 * esize}
+    W_last = {r["name"]: float(r["W"][-1].item()) for r in runs}
+    mass_drift = {r["name"]: float(((r["mom"][0::4] - r["mom"][0]).abs().max() / r["mom"][0]).item())
+                  for r in runs}
+
+    out = {
+        "metric": "4D dof-updates/s per advection sweep (whole Strang steps, SLDG + spline)",
+        "value": value,
+        "unit": "dof-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": elapsed / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dt,
+        "data": "synthetic (Landau initial condition sampled on the device)",
+        "config": {"workload": f"{w.name}: nonlinear Landau 2D-2V, {w.cells[0]}^4 cells, "
+                               f"SLDG degree {w.degree} ({dims[0]}^4 dofs) + cubic spline "
+                               f"on {dims[0]}^4 points, dt={w.dt}",
+                   "dofs": list(dims), "methods": methods, "sweeps_per_step": sweeps},
+        "roofline": roofline,
+        "kernels": detail,
+        "W_el_last": W_last,
+        "rel_mass_drift": mass_drift,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, dt)
+    for r in runs:
+        r["st"].close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,348 @@
+// Velocity moments (density and diagnostics) and initial conditions.
+//
+// rho(x1, x2) = int f dv (Sec. 2) and the diagnostics of Sec. 4 (mass, L1,
+// L2, kinetic energy) are read-only reductions over the contiguous
+// (v1, v2) block that belongs to every (x1, x2) point.  One workgroup owns
+// one block: it reads the block row by row with contiguous loads, weights
+// every value with the nodal quadrature (Gauss-Legendre weights times the
+// cell width for SLDG, the spacing for the spline grid) and reduces in FP64,
+// within each 64-lane wavefront by cross-lane shuffles and across the four
+// wavefronts through LDS.  No atomics, so results are deterministic.
+#include <cmath>
+
+#include "vp4d_internal.hpp"
+#include "field.hpp"
+
+namespace vp {
+
+AxisGrid axis_grid(int degree, int64_t n, double lo, double len) {
+    AxisGrid a{};
+    a.lo = lo;
+    if (degree < 0) {
+        a.m = 1;
+        a.w[0] = 1.0;
+        a.xi[0] = 0.5;
+        a.h = len / static_cast<double>(n);
+    } else {
+        const NodeBasis& b = node_basis(degree);
+        a.m = b.m;
+        for (int j = 0; j < b.m; ++j) {
+            a.w[j] = b.w[j];
+            a.xi[j] = b.xi[j];
+        }
+        a.h = len / static_cast<double>(n / b.m);
+    }
+    return a;
+}
+
+namespace {
+
+__device__ __forceinline__ double node_coord(const AxisGrid& g, int64_t c) {
+    const int64_t cell = c / g.m;
+    return g.lo + (static_cast<double>(cell) + g.xi[c - cell * g.m]) * g.h;
+}
+
+__device__ __forceinline__ double node_weight(const AxisGrid& g, int64_t c) {
+    return g.w[c % g.m] * g.h;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sums NV values over the workgroup; the result is valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double v[NV], double* red) {
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) red[wv * NV + q] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double s = 0.0;
+            for (int k = 0; k < kRedBlock / 64; ++k) s += red[k * NV + q];
+            v[q] = s;
+        }
+    }
+}
+
+// Per (x1,x2) block b: out[b] = sum_{c,e} W3_c W4_e f, and when DIAG also
+// out[nblk + b] = sum W |f|, out[2 nblk + b] = sum W f^2 and
+// out[3 nblk + b] = sum W (v1^2 + v2^2) f.
+template <typename T, bool DIAG>
+__global__ void __launch_bounds__(kRedBlock)
+velocity_reduce(const T* __restrict__ f, int n3, int n4, AxisGrid g3,
+                AxisGrid g4, double* __restrict__ out, int64_t nblk) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* wt3 = reinterpret_cast<double*>(smem);
+    double* wt4 = wt3 + n3;
+    double* vq3 = wt4 + n4;              // v^2 tables, DIAG only
+    double* vq4 = vq3 + (DIAG ? n3 : 0);
+    __shared__ double red[4 * (kRedBlock / 64)];
+
+    for (int c = threadIdx.x; c < n3; c += kRedBlock) {
+        wt3[c] = node_weight(g3, c);
+        if (DIAG) {
+            const double v = node_coord(g3, c);
+            vq3[c] = v * v;
+        }
+    }
+    for (int e = threadIdx.x; e < n4; e += kRedBlock) {
+        wt4[e] = node_weight(g4, e);
+        if (DIAG) {
+            const double v = node_coord(g4, e);
+            vq4[e] = v * v;
+        }
+    }
+    __syncthreads();
+
+    const int64_t b = blockIdx.x;
+    const T* __restrict__ blk = f + b * static_cast<int64_t>(n3) * n4;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = wv; c < n3; c += kRedBlock / 64) {
+        const T* __restrict__ row = blk + static_cast<int64_t>(c) * n4;
+        double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+        for (int e = lane; e < n4; e += 64) {
+            const double x = static_cast<double>(row[e]);
+            const double we = wt4[e];
+            r0 = fma(we, x, r0);
+            if (DIAG) {
+                r1 = fma(we, fabs(x), r1);
+                r2 = fma(we * x, x, r2);
+                r3 = fma(we * x, vq4[e], r3);
+            }
+        }
+        const double wc = wt3[c];
+        acc[0] = fma(wc, r0, acc[0]);
+        if (DIAG) {
+            acc[1] = fma(wc, r1, acc[1]);
+            acc[2] = fma(wc, r2, acc[2]);
+            // sum W (v1^2 + v2^2) f = v1^2 * sum W f + sum W v2^2 f
+            acc[3] = fma(wc, fma(vq3[c], r0, r3), acc[3]);
+        }
+    }
+    if (DIAG) {
+        block_sum<4>(acc, red);
+        if (threadIdx.x == 0) {
+            out[b] = acc[0];
+            out[nblk + b] = acc[1];
+            out[2 * nblk + b] = acc[2];
+            out[3 * nblk + b] = acc[3];
+        }
+    } else {
+        block_sum<1>(acc, red);
+        if (threadIdx.x == 0) out[b] = acc[0];
+    }
+}
+
+// out4 = (mass, L1, L2, kinetic) from the per-(x1,x2) partial sums.
+__global__ void __launch_bounds__(kRedBlock)
+moments_final(const double* __restrict__ part, int n1, int n2, AxisGrid g1,
+              AxisGrid g2, double* __restrict__ out4) {
+    __shared__ double red[4 * (kRedBlock / 64)];
+    const int64_t nblk = static_cast<int64_t>(n1) * n2;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t q = threadIdx.x; q < nblk; q += kRedBlock) {
+        const int64_t a = q / n2;
+        const double w = node_weight(g1, a) * node_weight(g2, q - a * n2);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] = fma(w, part[k * nblk + q], acc[k]);
+    }
+    block_sum<4>(acc, red);
+    if (threadIdx.x == 0) {
+        out4[0] = acc[0];
+        out4[1] = acc[1];
+        out4[2] = sqrt(acc[2]);
+        out4[3] = 0.5 * acc[3];
+    }
+}
+
+struct IcParams {
+    int kind;
+    double eps, k, v0;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+init_kernel(T* __restrict__ f, int64_t total, int64_t n2, int64_t n3,
+            int64_t n4, AxisGrid g1, AxisGrid g2, AxisGrid g3, AxisGrid g4,
+            IcParams p) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+         idx < total; idx += stride) {
+        int64_t r = idx;
+        const int64_t i4 = r % n4;
+        r /= n4;
+        const int64_t i3 = r % n3;
+        r /= n3;
+        const int64_t i2 = r % n2;
+        const int64_t i1 = r / n2;
+        const double x1 = node_coord(g1, i1), x2 = node_coord(g2, i2);
+        const double v1 = node_coord(g3, i3), v2 = node_coord(g4, i4);
+        double val;
+        if (p.kind == 0) {
+            val = (1.0 + p.eps * (cos(p.k * x1) + cos(p.k * x2))) *
+                  exp(-0.5 * (v1 * v1 + v2 * v2)) * (0.5 / M_PI);
+        } else {
+            const double px = p.kind == 1
+                                  ? 1.0 + p.eps * (cos(p.k * x1) + cos(p.k * x2))
+                                  : 1.0 + p.eps * cos(p.k * x1) * cos(p.k * x2);
+            const double a1 = v1 - p.v0, b1 = v1 + p.v0;
+            const double a2 = v2 - p.v0, b2 = v2 + p.v0;
+            const double g1v = exp(-0.5 * a1 * a1) + exp(-0.5 * b1 * b1);
+            const double g2v = exp(-0.5 * a2 * a2) + exp(-0.5 * b2 * b2);
+            val = px * g1v * g2v * (0.125 / M_PI);
+        }
+        f[idx] = static_cast<T>(val);
+    }
+}
+
+template <typename T>
+vp_status launch_reduce(bool diag, const int64_t dims[4], const void* f,
+                        const AxisGrid& g3, const AxisGrid& g4, double* out,
+                        hipStream_t st) {
+    const int64_t nblk = dims[0] * dims[1];
+    const int n3 = static_cast<int>(dims[2]), n4 = static_cast<int>(dims[3]);
+    const size_t lds = (diag ? 2 : 1) * sizeof(double) * (static_cast<size_t>(n3) + n4);
+    if (lds > 48 * 1024)
+        return set_error(VP_ERR_UNSUPPORTED, "velocity axes of %d x %d nodes too long", n3, n4);
+    if (nblk >= (int64_t(1) << 31))
+        return set_error(VP_ERR_UNSUPPORTED, "too many (x1, x2) points");
+    const T* fp = static_cast<const T*>(f);
+    if (diag)
+        velocity_reduce<T, true><<<static_cast<unsigned>(nblk), kRedBlock, lds, st>>>(
+            fp, n3, n4, g3, g4, out, nblk);
+    else
+        velocity_reduce<T, false><<<static_cast<unsigned>(nblk), kRedBlock, lds, st>>>(
+            fp, n3, n4, g3, g4, out, nblk);
+    return check_launch("velocity_reduce");
+}
+
+}  // namespace
+
+vp_status density_impl(int degree, vp_dtype dt, const int64_t dims[4],
+                       const void* f, double len_v1, double len_v2, double* rho,
+                       hipStream_t st) {
+    const AxisGrid g3 = axis_grid(degree, dims[2], 0.0, len_v1);
+    const AxisGrid g4 = axis_grid(degree, dims[3], 0.0, len_v2);
+    if (dt == VP_F64) return launch_reduce<double>(false, dims, f, g3, g4, rho, st);
+    return launch_reduce<float>(false, dims, f, g3, g4, rho, st);
+}
+
+vp_status moments_partial_impl(int degree, vp_dtype dt, const int64_t dims[4],
+                               const void* f, const double lo[4],
+                               const double len[4], double* partial,
+                               hipStream_t st) {
+    const AxisGrid g3 = axis_grid(degree, dims[2], lo[2], len[2]);
+    const AxisGrid g4 = axis_grid(degree, dims[3], lo[3], len[3]);
+    if (dt == VP_F64) return launch_reduce<double>(true, dims, f, g3, g4, partial, st);
+    return launch_reduce<float>(true, dims, f, g3, g4, partial, st);
+}
+
+vp_status moments_final_impl(int degree, const int64_t dims[4],
+                             const double lo[4], const double len[4],
+                             const double* partial, double* out4,
+                             hipStream_t st) {
+    const AxisGrid g1 = axis_grid(degree, dims[0], lo[0], len[0]);
+    const AxisGrid g2 = axis_grid(degree, dims[1], lo[1], len[1]);
+    moments_final<<<1, kRedBlock, 0, st>>>(partial, static_cast<int>(dims[0]),
+                                           static_cast<int>(dims[1]), g1, g2, out4);
+    return check_launch("moments_final");
+}
+
+static vp_status check_degree_dims(int degree, const int64_t dims[4], int64_t* total) {
+    if (degree < -1 || degree > VP_MAX_DEGREE)
+        return set_error(VP_ERR_UNSUPPORTED, "degree %d not in -1..%d", degree, VP_MAX_DEGREE);
+    vp_status rc = check_dims(dims, total);
+    if (rc != VP_OK) return rc;
+    if (degree >= 0)
+        for (int d = 0; d < 4; ++d)
+            if (dims[d] % (degree + 1))
+                return set_error(VP_ERR_ARG, "dims[%d] = %lld not a multiple of %d", d,
+                                 (long long)dims[d], degree + 1);
+    return VP_OK;
+}
+
+vp_status check_grid_args(int degree, vp_dtype dt, const int64_t dims[4], int64_t* total) {
+    if (dt != VP_F32 && dt != VP_F64) return set_error(VP_ERR_ARG, "bad dtype %d", (int)dt);
+    return check_degree_dims(degree, dims, total);
+}
+
+}  // namespace vp
+
+using namespace vp;
+
+extern "C" vp_status vp_density(int degree, vp_dtype dt, const int64_t dims[4],
+                                const void* f, double len_v1, double len_v2,
+                                double* rho, void* stream) {
+    clear_error();
+    int64_t total = 0;
+    vp_status rc = check_grid_args(degree, dt, dims, &total);
+    if (rc != VP_OK) return rc;
+    if (!f || !rho) return set_error(VP_ERR_ARG, "NULL pointer argument");
+    if (!(len_v1 > 0.0) || !(len_v2 > 0.0))
+        return set_error(VP_ERR_ARG, "velocity box lengths must be positive");
+    return density_impl(degree, dt, dims, f, len_v1, len_v2, rho,
+                        static_cast<hipStream_t>(stream));
+}
+
+extern "C" size_t vp_moments_workspace(const int64_t dims[4]) {
+    if (!dims || dims[0] < 1 || dims[1] < 1) return 0;
+    return 4 * sizeof(double) * static_cast<size_t>(dims[0]) * static_cast<size_t>(dims[1]);
+}
+
+extern "C" vp_status vp_moments(int degree, vp_dtype dt, const int64_t dims[4],
+                                const void* f, const double lo[4],
+                                const double len[4], double* out4,
+                                void* workspace, size_t ws_bytes, void* stream) {
+    clear_error();
+    int64_t total = 0;
+    vp_status rc = check_grid_args(degree, dt, dims, &total);
+    if (rc != VP_OK) return rc;
+    if (!f || !out4 || !lo || !len) return set_error(VP_ERR_ARG, "NULL pointer argument");
+    for (int d = 0; d < 4; ++d)
+        if (!(len[d] > 0.0)) return set_error(VP_ERR_ARG, "len[%d] must be positive", d);
+    if (!workspace || ws_bytes < vp_moments_workspace(dims))
+        return set_error(VP_ERR_WORKSPACE, "workspace of %zu bytes needed",
+                         vp_moments_workspace(dims));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double* part = static_cast<double*>(workspace);
+    rc = moments_partial_impl(degree, dt, dims, f, lo, len, part, st);
+    if (rc != VP_OK) return rc;
+    return moments_final_impl(degree, dims, lo, len, part, out4, st);
+}
+
+extern "C" vp_status vp_init(int kind, double eps, double k, double v0, int degree,
+                             vp_dtype dt, const int64_t dims[4], const double lo[4],
+                             const double len[4], void* f, void* stream) {
+    clear_error();
+    int64_t total = 0;
+    vp_status rc = check_grid_args(degree, dt, dims, &total);
+    if (rc != VP_OK) return rc;
+    if (kind < 0 || kind > 2) return set_error(VP_ERR_ARG, "initial condition kind %d", kind);
+    if (!f || !lo || !len) return set_error(VP_ERR_ARG, "NULL pointer argument");
+    for (int d = 0; d < 4; ++d)
+        if (!(len[d] > 0.0)) return set_error(VP_ERR_ARG, "len[%d] must be positive", d);
+    AxisGrid g[4];
+    for (int d = 0; d < 4; ++d) g[d] = axis_grid(degree, dims[d], lo[d], len[d]);
+    IcParams p{kind, eps, k, v0};
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (dt == VP_F64)
+        init_kernel<double><<<static_cast<unsigned>(blocks), 256, 0, st>>>(
+            static_cast<double*>(f), total, dims[1], dims[2], dims[3], g[0], g[1], g[2], g[3], p);
+    else
+        init_kernel<float><<<static_cast<unsigned>(blocks), 256, 0, st>>>(
+            static_cast<float*>(f), total, dims[1], dims[2], dims[3], g[0], g[1], g[2], g[3], p);
+    return check_launch("init_kernel");
+}

@@ -1,0 +1,313 @@
+// SLDG translate-and-project sweep (Sec. 2, last part; Sec. 3, Eq. (5)).
+//
+// A line of n_c cells x m = degree+1 Gauss-Legendre dofs is shifted by
+// sigma cells: with s = floor(sigma) mod n_c and alpha = sigma - floor(sigma),
+// output cell i = A(alpha) u_{i-s-1} + B(alpha) u_{i-s}.  The per-line
+// operator (s, A, B) is built in FP64 inside the kernel from the quadrature
+// definition
+//   A_jl = (alpha/w_j) sum_q w_q L_l(alpha xi_q + 1 - alpha) L_j(alpha xi_q)
+//   B_jl = ((1-alpha)/w_j) sum_q w_q L_l((1-alpha) xi_q) L_j(alpha + (1-alpha) xi_q)
+// (the (m)-point Gauss rule is exact for these degree-2l integrands) and
+// rounded to the storage type T; the sweep itself is 2m FMAs per dof in T.
+//
+// Two kernels, both HBM-bound (each dof read once and written once):
+//  * sldg_col  -- axes whose lines are strided (x1, x2, v1).  One thread per
+//    line streams the cells of its line in memory order; adjacent threads own
+//    adjacent lines, so every load and store of a wavefront is contiguous
+//    along the fastest axis.  Each input cell is loaded exactly once: the
+//    last cell is loaded first (it is the left neighbour of cell 0) and
+//    reused at the end.
+//  * sldg_row  -- the contiguous axis (v2).  A workgroup stages R whole
+//    lines in LDS with contiguous loads, builds the R line operators once,
+//    and every thread produces one output cell from two LDS cells.
+#include "vp4d_internal.hpp"
+
+namespace vp {
+namespace {
+
+constexpr int kBlock = 256;
+
+template <int M>
+__device__ __forceinline__ void lagrange_all(const NodeBasis& b, double t,
+                                             double L[M]) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        double p = 1.0;
+#pragma unroll
+        for (int k = 0; k < M; ++k)
+            if (k != j) p *= (t - b.xi[k]) * b.rd[j][k];
+        L[j] = p;
+    }
+}
+
+// Builds the line operator.  alpha == 0 gives A = 0, B = I exactly, so a
+// whole-cell shift is an exact permutation of the cells.
+template <int M, typename T>
+__device__ __forceinline__ void sldg_operator(const NodeBasis& b, double sigma,
+                                              int nc, int& s, T A[M][M],
+                                              T B[M][M]) {
+    double alpha;
+    if (!split_shift(sigma, nc, s, alpha)) {
+        const T nan = T(__builtin_nan(""));
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+#pragma unroll
+            for (int l = 0; l < M; ++l) A[j][l] = B[j][l] = nan;
+        return;
+    }
+    if (alpha == 0.0) {
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                A[j][l] = T(0);
+                B[j][l] = T(j == l ? 1 : 0);
+            }
+        return;
+    }
+    const double beta = 1.0 - alpha;
+    double a[M][M], c[M][M];
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+#pragma unroll
+        for (int l = 0; l < M; ++l) a[j][l] = c[j][l] = 0.0;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        double lo[M], li[M], ro[M], ri[M];
+        const double ta = alpha * b.xi[q];
+        lagrange_all<M>(b, ta, lo);
+        lagrange_all<M>(b, ta + beta, li);
+        lagrange_all<M>(b, alpha + beta * b.xi[q], ro);
+        lagrange_all<M>(b, beta * b.xi[q], ri);
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const double wl = b.w[q] * lo[j];
+            const double wr = b.w[q] * ro[j];
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                a[j][l] = fma(wl, li[l], a[j][l]);
+                c[j][l] = fma(wr, ri[l], c[j][l]);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const double sa = alpha * b.inv_w[j];
+        const double sb = beta * b.inv_w[j];
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            A[j][l] = T(a[j][l] * sa);
+            B[j][l] = T(c[j][l] * sb);
+        }
+    }
+}
+
+template <int M, typename T, int AXIS>
+__global__ void __launch_bounds__(kBlock)
+sldg_col(const T* __restrict__ fin, T* __restrict__ fout,
+         const double* __restrict__ shift, ShiftMap sm, int64_t outer, int nc,
+         int64_t inner, NodeBasis basis) {
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (gid >= outer * inner) return;
+    const int64_t o = gid / inner;
+    const int64_t k = gid - o * inner;
+
+    int s;
+    T A[M][M], B[M][M];
+    sldg_operator<M, T>(basis, shift[shift_offset(sm, o, k)], nc, s, A, B);
+
+    const int64_t cs = static_cast<int64_t>(M) * inner;  // cell stride
+    const T* __restrict__ src = fin + o * nc * cs + k;
+    T* __restrict__ dst = fout + o * nc * cs + k;
+
+    T last[M], prev[M];
+#pragma unroll
+    for (int l = 0; l < M; ++l) {
+        last[l] = src[(nc - 1) * cs + l * inner];
+        prev[l] = last[l];
+    }
+    int i = s;  // output cell fed by input cells (c-1, c)
+#pragma unroll 2
+    for (int c = 0; c < nc; ++c) {
+        T cur[M];
+        if (c < nc - 1) {
+#pragma unroll
+            for (int l = 0; l < M; ++l) cur[l] = src[c * cs + l * inner];
+        } else {
+#pragma unroll
+            for (int l = 0; l < M; ++l) cur[l] = last[l];
+        }
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            T acc = T(0);
+#pragma unroll
+            for (int l = 0; l < M; ++l) acc = fma(A[j][l], prev[l], acc);
+#pragma unroll
+            for (int l = 0; l < M; ++l) acc = fma(B[j][l], cur[l], acc);
+            dst[i * cs + j * inner] = acc;
+        }
+#pragma unroll
+        for (int l = 0; l < M; ++l) prev[l] = cur[l];
+        if (++i == nc) i = 0;
+    }
+}
+
+template <int M, typename T>
+__global__ void __launch_bounds__(kBlock)
+sldg_row(const T* __restrict__ fin, T* __restrict__ fout,
+         const double* __restrict__ shift, ShiftMap sm, int64_t nrows, int nc,
+         int R, NodeBasis basis) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = nc * M;
+    T* tile = reinterpret_cast<T*>(smem);              // R * N
+    T* ops = tile + R * N;                             // R * 2 M^2
+    int* sh = reinterpret_cast<int*>(ops + R * 2 * M * M);
+
+    const int64_t row0 = static_cast<int64_t>(blockIdx.x) * R;
+    const int nr = static_cast<int>(min(static_cast<int64_t>(R), nrows - row0));
+
+    for (int r = threadIdx.x; r < nr; r += kBlock) {
+        int s;
+        T A[M][M], B[M][M];
+        sldg_operator<M, T>(basis, shift[shift_offset(sm, row0 + r, 0)], nc, s,
+                            A, B);
+        T* op = ops + r * 2 * M * M;
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                op[j * M + l] = A[j][l];
+                op[M * M + j * M + l] = B[j][l];
+            }
+        sh[r] = s;
+    }
+    const int64_t base = row0 * N;
+    const int cnt = nr * N;
+    for (int e = threadIdx.x; e < cnt; e += kBlock) tile[e] = fin[base + e];
+    __syncthreads();
+
+    const int ncell = nr * nc;
+    for (int q = threadIdx.x; q < ncell; q += kBlock) {
+        const int r = q / nc;
+        const int i = q - r * nc;
+        const int s = sh[r];
+        int left = i - s - 1;
+        if (left < 0) left += nc;
+        int right = i - s;
+        if (right < 0) right += nc;
+        const T* op = ops + r * 2 * M * M;
+        const T* ul = tile + r * N + left * M;
+        const T* ur = tile + r * N + right * M;
+        T u0[M], u1[M];
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            u0[l] = ul[l];
+            u1[l] = ur[l];
+        }
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            T acc = T(0);
+#pragma unroll
+            for (int l = 0; l < M; ++l) acc = fma(op[j * M + l], u0[l], acc);
+#pragma unroll
+            for (int l = 0; l < M; ++l) acc = fma(op[M * M + j * M + l], u1[l], acc);
+            fout[base + static_cast<int64_t>(r) * N + i * M + j] = acc;
+        }
+    }
+}
+
+template <int M, typename T>
+vp_status launch_sldg(int axis, const int64_t dims[4], const void* fin,
+                      void* fout, const double* shift, const ShiftMap& sm,
+                      hipStream_t st) {
+    const NodeBasis& b = node_basis(M - 1);
+    int64_t outer = 1, inner = 1;
+    for (int d = 0; d < axis; ++d) outer *= dims[d];
+    for (int d = axis + 1; d < 4; ++d) inner *= dims[d];
+    const int nc = static_cast<int>(dims[axis] / M);
+    const T* in = static_cast<const T*>(fin);
+    T* out = static_cast<T*>(fout);
+    if (axis < 3) {
+        const unsigned grid = blocks_for(outer * inner, kBlock);
+        switch (axis) {
+            case 0:
+                sldg_col<M, T, 0><<<grid, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, b);
+                break;
+            case 1:
+                sldg_col<M, T, 1><<<grid, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, b);
+                break;
+            default:
+                sldg_col<M, T, 2><<<grid, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, b);
+                break;
+        }
+        return check_launch("sldg_col");
+    }
+    const int N = static_cast<int>(dims[3]);
+    int R = 4096 / N;
+    if (R < 1) R = 1;
+    if (R > kBlock) R = kBlock;
+    const size_t lds = static_cast<size_t>(R) * N * sizeof(T) +
+                       static_cast<size_t>(R) * 2 * M * M * sizeof(T) +
+                       static_cast<size_t>(R) * sizeof(int);
+    if (lds > 64 * 1024)
+        return set_error(VP_ERR_UNSUPPORTED,
+                         "sldg_advect: line of %d dofs too long for the LDS tile", N);
+    const unsigned grid = blocks_for(outer, R);
+    sldg_row<M, T><<<grid, kBlock, lds, st>>>(in, out, shift, sm, outer, nc, R, b);
+    return check_launch("sldg_row");
+}
+
+template <typename T>
+vp_status dispatch_degree(int degree, int axis, const int64_t dims[4],
+                          const void* fin, void* fout, const double* shift,
+                          const ShiftMap& sm, hipStream_t st) {
+    switch (degree) {
+        case 0: return launch_sldg<1, T>(axis, dims, fin, fout, shift, sm, st);
+        case 1: return launch_sldg<2, T>(axis, dims, fin, fout, shift, sm, st);
+        case 2: return launch_sldg<3, T>(axis, dims, fin, fout, shift, sm, st);
+        case 3: return launch_sldg<4, T>(axis, dims, fin, fout, shift, sm, st);
+        case 4: return launch_sldg<5, T>(axis, dims, fin, fout, shift, sm, st);
+        case 5: return launch_sldg<6, T>(axis, dims, fin, fout, shift, sm, st);
+        default: return set_error(VP_ERR_UNSUPPORTED, "degree %d", degree);
+    }
+}
+
+}  // namespace
+
+vp_status sldg_advect_impl(int axis, int degree, vp_dtype dt,
+                           const int64_t dims[4], const void* f_in, void* f_out,
+                           const double* shift, const int64_t shift_stride[4],
+                           hipStream_t st) {
+    const ShiftMap sm = make_shift_map(axis, dims, shift_stride);
+    if (dt == VP_F64)
+        return dispatch_degree<double>(degree, axis, dims, f_in, f_out, shift, sm, st);
+    return dispatch_degree<float>(degree, axis, dims, f_in, f_out, shift, sm, st);
+}
+
+}  // namespace vp
+
+extern "C" vp_status sldg_advect(int axis, int degree, vp_dtype dt,
+                                 const int64_t dims[4], const void* f_in,
+                                 void* f_out, const double* shift,
+                                 const int64_t shift_stride[4], void* stream) {
+    using namespace vp;
+    clear_error();
+    if (axis < 0 || axis > 3) return set_error(VP_ERR_ARG, "axis %d not in 0..3", axis);
+    if (degree < 0 || degree > VP_MAX_DEGREE)
+        return set_error(VP_ERR_UNSUPPORTED, "degree %d not in 0..%d", degree,
+                         VP_MAX_DEGREE);
+    if (dt != VP_F32 && dt != VP_F64) return set_error(VP_ERR_ARG, "bad dtype %d", (int)dt);
+    int64_t total = 0;
+    vp_status rc = check_dims(dims, &total);
+    if (rc != VP_OK) return rc;
+    if (dims[axis] % (degree + 1))
+        return set_error(VP_ERR_ARG, "dims[%d] = %lld is not a multiple of degree+1 = %d",
+                         axis, (long long)dims[axis], degree + 1);
+    if (!f_in || !f_out || !shift) return set_error(VP_ERR_ARG, "NULL pointer argument");
+    rc = check_shift_strides(axis, dims, shift_stride);
+    if (rc != VP_OK) return rc;
+    if (ranges_overlap(f_in, f_out, static_cast<size_t>(total) * dtype_size(dt)))
+        return set_error(VP_ERR_ALIAS, "f_in and f_out overlap");
+    return sldg_advect_impl(axis, degree, dt, dims, f_in, f_out, shift, shift_stride,
+                            static_cast<hipStream_t>(stream));
+}

@@ -1,0 +1,300 @@
+// Strang splitting time step (Sec. 2) on one HIP stream.
+//
+//   f^{m+1} = exp(tau/2 A) exp(tau B) exp(tau/2 A) f^m
+//
+// with A split into the x1 and x2 free-streaming sweeps and B into the v1
+// and v2 acceleration sweeps (the directional parts commute, so the split
+// adds no error).  E is computed from the density after the first half step
+// and stays fixed during B, which leaves the density unchanged.  Every sweep
+// reads one buffer and writes the other; six sweeps per step return the
+// result to the caller's buffer.  No host synchronisation inside a step.
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "field.hpp"
+
+struct vp_state {
+    int device;
+    int method;  // 0 SLDG, 1 spline
+    int degree;  // SLDG degree, -1 for the spline grid
+    vp_dtype dt;
+    int64_t dims[4];
+    double lo[4], len[4];
+    double h[4];  // shift unit per axis: cell width or grid spacing
+    double* buf;  // one device allocation holding every 2D array below
+    double *rho, *e1, *e2, *sig_v1, *sig_v2, *sig_x1, *sig_x2, *vnode1, *vnode2;
+    double* partial;  // 4 * n1 * n2
+    void* pws;        // Poisson workspace
+    bool timing;
+    std::vector<hipEvent_t> ev[VP_TIMER_COUNT];  // start/stop pairs
+    std::vector<hipEvent_t> free_events;
+};
+
+namespace vp {
+namespace {
+
+__global__ void scale2(const double* __restrict__ a, const double* __restrict__ b,
+                       double sa, double sb, double* __restrict__ oa,
+                       double* __restrict__ ob, int64_t n) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) {
+        oa[i] = sa * a[i];
+        ob[i] = sb * b[i];
+    }
+}
+
+__global__ void xshift(const double* __restrict__ v1, const double* __restrict__ v2,
+                       int64_t n3, int64_t n4, double s1, double s2,
+                       double* __restrict__ o1, double* __restrict__ o2) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n3) o1[i] = s1 * v1[i];
+    if (i < n4) o2[i] = s2 * v2[i];
+}
+
+hipEvent_t take_event(vp_state* st) {
+    if (!st->free_events.empty()) {
+        hipEvent_t e = st->free_events.back();
+        st->free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void mark(vp_state* st, int timer, hipStream_t s) {
+    if (!st->timing) return;
+    hipEvent_t e = take_event(st);
+    if (!e) return;
+    (void)hipEventRecord(e, s);
+    st->ev[timer].push_back(e);
+}
+
+vp_status sweep(vp_state* st, int axis, const void* in, void* out,
+                const double* shift, hipStream_t s) {
+    int64_t stride[4] = {0, 0, 0, 0};
+    if (axis == 0) stride[2] = 1;
+    else if (axis == 1) stride[3] = 1;
+    else {
+        stride[0] = st->dims[1];
+        stride[1] = 1;
+    }
+    mark(st, VP_TIMER_SWEEP_X1 + axis, s);
+    vp_status rc = st->method == 0
+                       ? sldg_advect_impl(axis, st->degree, st->dt, st->dims, in, out,
+                                          shift, stride, s)
+                       : spline_advect_impl(axis, st->dt, st->dims, in, out, shift,
+                                            stride, s);
+    mark(st, VP_TIMER_SWEEP_X1 + axis, s);
+    return rc;
+}
+
+// W (and optionally the moments) of the state in f.
+vp_status diagnostics(vp_state* st, const void* f, double* W, double* mom,
+                      hipStream_t s) {
+    mark(st, VP_TIMER_DIAG, s);
+    vp_status rc;
+    if (mom) {
+        rc = moments_partial_impl(st->degree, st->dt, st->dims, f, st->lo, st->len,
+                                  st->partial, s);
+        if (rc == VP_OK)
+            rc = moments_final_impl(st->degree, st->dims, st->lo, st->len, st->partial,
+                                    mom, s);
+        if (rc == VP_OK && W)
+            rc = poisson_impl(st->degree, st->dims[0], st->dims[1], st->len[0],
+                              st->len[1], st->partial, st->e1, st->e2, W, st->pws, s);
+    } else {
+        rc = density_impl(st->degree, st->dt, st->dims, f, st->len[2], st->len[3],
+                          st->rho, s);
+        if (rc == VP_OK)
+            rc = poisson_impl(st->degree, st->dims[0], st->dims[1], st->len[0],
+                              st->len[1], st->rho, st->e1, st->e2, W, st->pws, s);
+    }
+    mark(st, VP_TIMER_DIAG, s);
+    return rc;
+}
+
+}  // namespace
+}  // namespace vp
+
+using namespace vp;
+
+extern "C" vp_status vp_create(vp_state** out, int method, int degree, vp_dtype dt,
+                               const int64_t dims[4], const double lo[4],
+                               const double len[4]) {
+    clear_error();
+    if (!out) return set_error(VP_ERR_ARG, "st is NULL");
+    *out = nullptr;
+    if (method != 0 && method != 1) return set_error(VP_ERR_ARG, "method %d", method);
+    const int deg = method == 1 ? -1 : degree;
+    if (method == 0 && (degree < 0 || degree > VP_MAX_DEGREE))
+        return set_error(VP_ERR_UNSUPPORTED, "degree %d", degree);
+    int64_t total = 0;
+    vp_status rc = check_grid_args(deg, dt, dims, &total);
+    if (rc != VP_OK) return rc;
+    if (!lo || !len) return set_error(VP_ERR_ARG, "NULL pointer argument");
+    for (int d = 0; d < 4; ++d)
+        if (!(len[d] > 0.0)) return set_error(VP_ERR_ARG, "len[%d] must be positive", d);
+    if (dims[0] * dims[1] >= (int64_t(1) << 31))
+        return set_error(VP_ERR_UNSUPPORTED, "x grid too large");
+
+    int device = -1;
+    VP_HIP_TRY(hipGetDevice(&device));
+    vp_state* st = new (std::nothrow) vp_state();
+    if (!st) return set_error(VP_ERR_ARG, "out of host memory");
+    st->device = device;
+    st->method = method;
+    st->degree = deg;
+    st->dt = dt;
+    for (int d = 0; d < 4; ++d) {
+        st->dims[d] = dims[d];
+        st->lo[d] = lo[d];
+        st->len[d] = len[d];
+        st->h[d] = axis_grid(deg, dims[d], lo[d], len[d]).h;
+    }
+    const int64_t nx = dims[0] * dims[1];
+    const size_t pws = vp_poisson_workspace(deg, dims[0], dims[1]);
+    const size_t ndbl = static_cast<size_t>(nx) * (5 + 4) +
+                        2 * static_cast<size_t>(dims[2] + dims[3]) + pws / sizeof(double) + 64;
+    void* mem = nullptr;
+    hipError_t e = hipMalloc(&mem, ndbl * sizeof(double));
+    if (e != hipSuccess) {
+        delete st;
+        return set_error(VP_ERR_HIP, "hipMalloc of %zu bytes failed: %s", ndbl * sizeof(double),
+                         hipGetErrorString(e));
+    }
+    double* p = static_cast<double*>(mem);
+    st->buf = p;
+    st->rho = p; p += nx;
+    st->e1 = p; p += nx;
+    st->e2 = p; p += nx;
+    st->sig_v1 = p; p += nx;
+    st->sig_v2 = p; p += nx;
+    st->partial = p; p += 4 * nx;
+    st->sig_x1 = p; p += dims[2];
+    st->sig_x2 = p; p += dims[3];
+    st->vnode1 = p; p += dims[2];
+    st->vnode2 = p; p += dims[3];
+    p = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(p) + 255) & ~uintptr_t(255));
+    st->pws = p;
+    // velocity node coordinates, used for the x-sweep shifts
+    std::vector<double> v1(dims[2]), v2(dims[3]);
+    const AxisGrid g3 = axis_grid(deg, dims[2], lo[2], len[2]);
+    const AxisGrid g4 = axis_grid(deg, dims[3], lo[3], len[3]);
+    for (int64_t c = 0; c < dims[2]; ++c)
+        v1[c] = g3.lo + (static_cast<double>(c / g3.m) + g3.xi[c % g3.m]) * g3.h;
+    for (int64_t c = 0; c < dims[3]; ++c)
+        v2[c] = g4.lo + (static_cast<double>(c / g4.m) + g4.xi[c % g4.m]) * g4.h;
+    e = hipMemcpy(st->vnode1, v1.data(), sizeof(double) * dims[2], hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(st->vnode2, v2.data(), sizeof(double) * dims[3], hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        delete st;
+        return set_error(VP_ERR_HIP, "hipMemcpy failed: %s", hipGetErrorString(e));
+    }
+    st->timing = false;
+    *out = st;
+    return VP_OK;
+}
+
+extern "C" void vp_destroy(vp_state* st) {
+    if (!st) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != st->device) (void)hipSetDevice(st->device);
+    (void)hipDeviceSynchronize();
+    for (auto& v : st->ev)
+        for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    for (hipEvent_t e : st->free_events) (void)hipEventDestroy(e);
+    (void)hipFree(st->buf);
+    if (cur != st->device) (void)hipSetDevice(cur);
+    delete st;
+}
+
+extern "C" vp_status vp_strang_step(vp_state* st, void* f, void* f_tmp, int nsteps,
+                                    double tau, double* W_trace, double* moments,
+                                    void* stream) {
+    clear_error();
+    if (!st || !f || !f_tmp) return set_error(VP_ERR_ARG, "NULL pointer argument");
+    if (nsteps < 0) return set_error(VP_ERR_ARG, "nsteps %d < 0", nsteps);
+    if (!(tau == tau) || tau > 1e300 || tau < -1e300) return set_error(VP_ERR_ARG, "tau not finite");
+    const size_t bytes = static_cast<size_t>(st->dims[0] * st->dims[1] * st->dims[2] *
+                                             st->dims[3]) * dtype_size(st->dt);
+    if (ranges_overlap(f, f_tmp, bytes)) return set_error(VP_ERR_ALIAS, "f and f_tmp overlap");
+    int cur = -1;
+    VP_HIP_TRY(hipGetDevice(&cur));
+    if (cur != st->device)
+        return set_error(VP_ERR_ARG, "state belongs to device %d, current device is %d",
+                         st->device, cur);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t nx = st->dims[0] * st->dims[1];
+    vp_status rc = VP_OK;
+
+    // x-sweep shifts: (tau/2) v / h_x, one value per velocity node
+    const int64_t nv = st->dims[2] > st->dims[3] ? st->dims[2] : st->dims[3];
+    xshift<<<blocks_for(nv, 256), 256, 0, s>>>(st->vnode1, st->vnode2, st->dims[2],
+                                               st->dims[3], 0.5 * tau / st->h[0],
+                                               0.5 * tau / st->h[1], st->sig_x1,
+                                               st->sig_x2);
+    if ((rc = check_launch("xshift")) != VP_OK) return rc;
+
+    if (W_trace || moments) {
+        rc = diagnostics(st, f, W_trace, moments, s);
+        if (rc != VP_OK) return rc;
+    }
+    for (int m = 0; m < nsteps; ++m) {
+        if ((rc = sweep(st, 0, f, f_tmp, st->sig_x1, s)) != VP_OK) return rc;
+        if ((rc = sweep(st, 1, f_tmp, f, st->sig_x2, s)) != VP_OK) return rc;
+        mark(st, VP_TIMER_FIELD, s);
+        rc = density_impl(st->degree, st->dt, st->dims, f, st->len[2], st->len[3],
+                          st->rho, s);
+        if (rc == VP_OK)
+            rc = poisson_impl(st->degree, st->dims[0], st->dims[1], st->len[0],
+                              st->len[1], st->rho, st->e1, st->e2, nullptr, st->pws, s);
+        if (rc != VP_OK) return rc;
+        scale2<<<blocks_for(nx, 256), 256, 0, s>>>(st->e1, st->e2, tau / st->h[2],
+                                                   tau / st->h[3], st->sig_v1,
+                                                   st->sig_v2, nx);
+        if ((rc = check_launch("scale2")) != VP_OK) return rc;
+        mark(st, VP_TIMER_FIELD, s);
+        if ((rc = sweep(st, 2, f, f_tmp, st->sig_v1, s)) != VP_OK) return rc;
+        if ((rc = sweep(st, 3, f_tmp, f, st->sig_v2, s)) != VP_OK) return rc;
+        if ((rc = sweep(st, 0, f, f_tmp, st->sig_x1, s)) != VP_OK) return rc;
+        if ((rc = sweep(st, 1, f_tmp, f, st->sig_x2, s)) != VP_OK) return rc;
+        if (W_trace || moments) {
+            rc = diagnostics(st, f, W_trace ? W_trace + m + 1 : nullptr,
+                             moments ? moments + 4 * (m + 1) : nullptr, s);
+            if (rc != VP_OK) return rc;
+        }
+    }
+    return VP_OK;
+}
+
+extern "C" vp_status vp_timing_enable(vp_state* st, int enable) {
+    clear_error();
+    if (!st) return set_error(VP_ERR_ARG, "st is NULL");
+    st->timing = enable != 0;
+    return VP_OK;
+}
+
+extern "C" vp_status vp_timing_read(vp_state* st, double* ms, int64_t* counts) {
+    clear_error();
+    if (!st || !ms || !counts) return set_error(VP_ERR_ARG, "NULL pointer argument");
+    for (int t = 0; t < VP_TIMER_COUNT; ++t) {
+        auto& v = st->ev[t];
+        const size_t pairs = v.size() / 2;
+        if (pairs) VP_HIP_TRY(hipEventSynchronize(v[2 * pairs - 1]));
+        for (size_t i = 0; i < pairs; ++i) {
+            float x = 0.f;
+            VP_HIP_TRY(hipEventElapsedTime(&x, v[2 * i], v[2 * i + 1]));
+            ms[t] += x;
+            counts[t] += 1;
+        }
+        for (hipEvent_t e : v) st->free_events.push_back(e);
+        v.clear();
+    }
+    return VP_OK;
+}

@@ -1,0 +1,123 @@
+// Internal declarations shared by the translation units of libvp4d.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "vp4d.h"
+
+namespace vp {
+
+constexpr int kMaxNodes = VP_MAX_DEGREE + 1;
+
+// ----------------------------------------------------------- error state ---
+vp_status set_error(vp_status code, const char* fmt, ...);
+void clear_error();
+
+#define VP_HIP_TRY(expr)                                                     \
+    do {                                                                     \
+        hipError_t e_ = (expr);                                              \
+        if (e_ != hipSuccess)                                                \
+            return ::vp::set_error(VP_ERR_HIP, "%s failed: %s (%s:%d)",      \
+                                   #expr, hipGetErrorString(e_), __FILE__,   \
+                                   __LINE__);                                \
+    } while (0)
+
+// Checks the launch that was just enqueued.
+vp_status check_launch(const char* what);
+
+// --------------------------------------------------------- 1D node basis ---
+// Gauss-Legendre nodes on [0,1] (ascending), weights summing to one, and the
+// reciprocal node differences used to evaluate Lagrange polynomials.
+struct NodeBasis {
+    int m;                               // nodes per cell (degree + 1)
+    double xi[kMaxNodes];
+    double w[kMaxNodes];
+    double inv_w[kMaxNodes];
+    double rd[kMaxNodes][kMaxNodes];     // rd[j][k] = 1/(xi_j - xi_k), k != j
+};
+
+// Fills `b` for polynomial degree 0..VP_MAX_DEGREE (host, cached).
+const NodeBasis& node_basis(int degree);
+
+// Values of the cell polynomial at m equidistant sub-cell midpoints
+// (Q[p][l] = L_l((p+1/2)/m)) and the inverse map.
+struct TransferPair {
+    int m;
+    double q[kMaxNodes][kMaxNodes];
+    double qinv[kMaxNodes][kMaxNodes];
+};
+const TransferPair& transfer_pair(int degree);
+
+// -------------------------------------------------------- argument checks ---
+vp_status check_dims(const int64_t dims[4], int64_t* total);
+vp_status check_shift_strides(int axis, const int64_t dims[4],
+                              const int64_t stride[4]);
+bool ranges_overlap(const void* a, const void* b, size_t bytes);
+
+inline size_t dtype_size(vp_dtype dt) { return dt == VP_F64 ? 8 : 4; }
+
+// Decomposes the index of a line into the strided shift offset.  The
+// dimensions before the swept axis form the "outer" index, the ones after
+// it the "inner" index (C order).
+struct ShiftMap {
+    int n_out, n_in;
+    int64_t out_dim[3], out_str[3];
+    int64_t in_dim[3], in_str[3];
+};
+ShiftMap make_shift_map(int axis, const int64_t dims[4], const int64_t stride[4]);
+
+// (Unrolled with constant indices so that the map stays in registers.)
+__device__ __forceinline__ int64_t shift_offset(const ShiftMap& sm, int64_t o,
+                                                int64_t k) {
+    int64_t off = 0;
+#pragma unroll
+    for (int d = 2; d >= 0; --d) {
+        if (d < sm.n_out) {
+            const int64_t q = o / sm.out_dim[d];
+            off += (o - q * sm.out_dim[d]) * sm.out_str[d];
+            o = q;
+        }
+    }
+#pragma unroll
+    for (int d = 2; d >= 0; --d) {
+        if (d < sm.n_in) {
+            const int64_t q = k / sm.in_dim[d];
+            off += (k - q * sm.in_dim[d]) * sm.in_str[d];
+            k = q;
+        }
+    }
+    return off;
+}
+
+// Splits a shift into its cell offset reduced modulo n (0 <= s < n) and its
+// fractional part alpha in [0, 1).  Returns false for a non-finite or absurdly
+// large shift; s is then 0 so that every index stays in range.
+__device__ __forceinline__ bool split_shift(double sigma, int n, int& s,
+                                            double& alpha) {
+    if (!(fabs(sigma) < 4.0e18)) {
+        s = 0;
+        alpha = 0.0;
+        return false;
+    }
+    double fl = floor(sigma);
+    alpha = sigma - fl;
+    if (alpha >= 1.0) {  // a tiny negative sigma rounds alpha up to one
+        fl += 1.0;
+        alpha = 0.0;
+    }
+    long long q = static_cast<long long>(fl) % static_cast<long long>(n);
+    if (q < 0) q += n;
+    s = static_cast<int>(q);
+    return true;
+}
+
+// Launch geometry helpers.
+inline unsigned blocks_for(int64_t work, int per_block) {
+    return static_cast<unsigned>((work + per_block - 1) / per_block);
+}
+
+}  // namespace vp

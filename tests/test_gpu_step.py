@@ -1,0 +1,165 @@
+"""Strang step parity: vp_strang_step against the oracle step by step and over
+whole runs, plus full-size checks at the 96^4 workload that the bench times."""
+
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import (announce, assert_close, rel_l2, require_gpu, to_dev,
+                        to_host, torch)
+from oracle import field, sldg, spline, strang
+from vp_inputs import random_field, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _grid(w, method):
+    degree = w.degree if method == "sldg" else None
+    return strang.Grid(w.dofs, w.lo, w.length, degree)
+
+
+@pytest.mark.parametrize("method", ["sldg", "spline"])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_step_by_step_parity(method, dt):
+    vp = require_gpu()
+    w = workload("landau_8")
+    g = _grid(w, method)
+    f = field.initial_condition("landau", w.dofs, w.lo, w.length, g.degree, w.eps, w.k)
+    st = vp.VPState(vp.METHOD_SLDG if method == "sldg" else vp.METHOD_SPLINE,
+                    w.degree, torch.float64 if dt == "f64" else torch.float32,
+                    w.dofs, w.lo, w.length)
+    for m in range(3):
+        announce(f"strang step {method} {dt} step {m}")
+        fd = to_dev(f, dt)
+        tmp = torch.empty_like(fd)
+        st.step(fd, tmp, 1, w.dt)
+        f_in = to_host(to_dev(f, dt))          # what the device started from
+        ref = strang.step(f_in, g, w.dt)
+        assert_close(to_host(fd), ref, dt, f"step {m}")
+        f = ref
+    st.close()
+
+
+@pytest.mark.parametrize("method", ["sldg", "spline"])
+def test_whole_run_energy_and_moments(method):
+    vp = require_gpu()
+    w = workload("landau_8")
+    g = _grid(w, method)
+    deg = w.degree if method == "sldg" else -1
+    f0 = field.initial_condition("landau", w.dofs, w.lo, w.length, g.degree, w.eps, w.k)
+    _, W_ref, mom_ref = strang.run(f0, g, w.dt, w.steps, with_moments=True)
+    announce(f"whole run {method} {w.steps} steps")
+    st = vp.VPState(vp.METHOD_SLDG if method == "sldg" else vp.METHOD_SPLINE,
+                    w.degree, torch.float64, w.dofs, w.lo, w.length)
+    fd = torch.empty(w.dofs, dtype=torch.float64, device="cuda")
+    vp.vp_init(vp.IC_LANDAU, w.eps, w.k, 0.0, deg, fd, w.lo, w.length)
+    tmp = torch.empty_like(fd)
+    W = torch.empty(w.steps + 1, dtype=torch.float64, device="cuda")
+    mom = torch.empty(4 * (w.steps + 1), dtype=torch.float64, device="cuda")
+    st.step(fd, tmp, w.steps, w.dt, W, mom)
+    Wg = to_host(W)
+    mg = to_host(mom).reshape(-1, 4)
+    np.testing.assert_allclose(Wg, W_ref, rtol=1e-10, atol=0)
+    np.testing.assert_allclose(mg, mom_ref, rtol=1e-10, atol=0)
+    # mass to round-off along the whole run
+    assert np.max(np.abs(mg[:, 0] - mg[0, 0])) <= 1e-13 * mg[0, 0]
+    st.close()
+
+
+def test_chunked_run_equals_single_run_bitwise():
+    vp = require_gpu()
+    w = workload("landau_8")
+    announce("chunked vs single run")
+    st = vp.VPState(vp.METHOD_SLDG, w.degree, torch.float64, w.dofs, w.lo, w.length)
+    a = torch.empty(w.dofs, dtype=torch.float64, device="cuda")
+    vp.vp_init(vp.IC_LANDAU, w.eps, w.k, 0.0, w.degree, a, w.lo, w.length)
+    b = a.clone()
+    tmp = torch.empty_like(a)
+    st.step(a, tmp, 4, w.dt)
+    st.step(b, tmp, 2, w.dt)
+    st.step(b, tmp, 2, w.dt)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    st.close()
+
+
+# ----------------------------------------------- full size (96^4, bench) ---
+
+def _sample_lines(axis, dims, count, seed):
+    rng = np.random.default_rng(seed)
+    idx = []
+    for _ in range(count):
+        i = [int(rng.integers(0, d)) for d in dims]
+        i[axis] = slice(None)
+        idx.append(tuple(i))
+    return idx
+
+
+@pytest.mark.parametrize("method", ["sldg", "spline"])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_full_size_sweeps_sampled(method, dt):
+    # the 96^4 workload, shifts with the step's broadcast patterns; sampled
+    # lines are recomputed by the oracle one by one
+    vp = require_gpu()
+    w = workload("landau_32")
+    dims = w.dofs
+    announce(f"full size {method} {dt} {dims}: host input")
+    f = random_field(dims, seed=32, positive=True)
+    fin = to_dev(f, dt)
+    fr = f.astype(np.float32).astype(np.float64) if dt == "f32" else f
+    rng = np.random.default_rng(33)
+    out = torch.empty_like(fin)
+    for axis in range(4):
+        if axis < 2:
+            sig = rng.uniform(-1.6, 1.6, size=dims[axis + 2])
+            st = [0, 0, 0, 0]
+            st[axis + 2] = 1
+        else:
+            sig = rng.uniform(-0.9, 0.9, size=dims[0] * dims[1])
+            st = [dims[1], 1, 0, 0]
+        announce(f"full size {method} {dt} axis={axis}")
+        if method == "sldg":
+            vp.sldg_advect(axis, w.degree, fin, out, to_dev(sig), shift_stride=st)
+        else:
+            vp.spline_advect(axis, fin, out, to_dev(sig), shift_stride=st)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().astype(np.float64)
+        lines = _sample_lines(axis, dims, 64, seed=axis)
+        for ix in lines:
+            off = sum(ix[d] * st[d] for d in range(4) if d != axis)
+            u = fr[ix][None, :]
+            if method == "sldg":
+                ref = sldg.shift_lines(u, sig[off], w.degree)[0]
+            else:
+                ref = spline.shift_lines(u, sig[off])[0]
+            assert_close(got[ix], ref, dt, f"axis {axis} line {ix}")
+        # mass per swept line is conserved everywhere (a property at any size)
+        if method == "sldg":
+            _, wq = np.polynomial.legendre.leggauss(w.degree + 1)
+            wl = np.tile(wq, dims[axis] // (w.degree + 1))
+        else:
+            wl = np.ones(dims[axis])
+        shape = [1, 1, 1, 1]
+        shape[axis] = dims[axis]
+        m0 = np.tensordot(fr, wl, axes=([axis], [0]))
+        m1 = np.tensordot(got, wl, axes=([axis], [0]))
+        tol = 1e-12 if dt == "f64" else 1e-5
+        assert np.max(np.abs(m1 - m0)) <= tol * np.max(np.abs(m0))
+
+
+def test_full_size_step_parity_sldg_f64():
+    vp = require_gpu()
+    w = workload("landau_32")
+    g = _grid(w, "sldg")
+    announce("full size step sldg f64: oracle IC")
+    f0 = field.initial_condition("landau", w.dofs, w.lo, w.length, w.degree, w.eps, w.k)
+    ref = strang.step(f0, g, w.dt)
+    st = vp.VPState(vp.METHOD_SLDG, w.degree, torch.float64, w.dofs, w.lo, w.length)
+    fd = to_dev(f0)
+    tmp = torch.empty_like(fd)
+    announce("full size step sldg f64: device step")
+    st.step(fd, tmp, 1, w.dt)
+    got = to_host(fd)
+    assert_close(got, ref, "f64", "96^4 step")
+    st.close()
