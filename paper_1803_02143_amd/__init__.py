@@ -175,7 +175,8 @@ class VPState:
         _check("vp_create", lib().vp_create(
             ctypes.byref(self._h), int(method), int(degree), dt, _lib.i64x4(dims),
             _lib.dblx4(lo), _lib.dblx4(length)))
-        self.method, self.degree, self.dims = method, degree, tuple(dims)
+        self.method, self.degree, self.dims = method, degree, tuple(int(d) for d in dims)
+        self.dtype = torch.float64 if dt == VP_F64 else torch.float32
 
     def close(self):
         if self._h:
@@ -189,6 +190,9 @@ class VPState:
             pass
 
     def step(self, f, f_tmp, nsteps, tau, W_trace=None, moments=None, stream=None):
+        for t, n in ((f, "f"), (f_tmp, "f_tmp")):
+            if tuple(t.shape) != self.dims or t.dtype != self.dtype:
+                raise ValueError(f"{n} must be {self.dtype} of shape {self.dims}")
         _check("vp_strang_step", lib().vp_strang_step(
             self._h, _dev(f, "f"), _dev(f_tmp, "f_tmp"), int(nsteps), float(tau),
             None if W_trace is None else _f64(W_trace, "W_trace", nsteps + 1),
