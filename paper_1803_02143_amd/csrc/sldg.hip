@@ -243,12 +243,14 @@ vp_status launch_sldg(int axis, const int64_t dims[4], const void* fin,
         return check_launch("sldg_col");
     }
     const int N = static_cast<int>(dims[3]);
+    // rows per workgroup: about 4096 dofs, and at most 48 KiB of LDS
+    const size_t per_row = static_cast<size_t>(N) * sizeof(T) +
+                           static_cast<size_t>(2 * M * M) * sizeof(T) + sizeof(int);
     int R = 4096 / N;
     if (R < 1) R = 1;
     if (R > kBlock) R = kBlock;
-    const size_t lds = static_cast<size_t>(R) * N * sizeof(T) +
-                       static_cast<size_t>(R) * 2 * M * M * sizeof(T) +
-                       static_cast<size_t>(R) * sizeof(int);
+    while (R > 1 && R * per_row > 48 * 1024) R /= 2;
+    const size_t lds = R * per_row;
     if (lds > 64 * 1024)
         return set_error(VP_ERR_UNSUPPORTED,
                          "sldg_advect: line of %d dofs too long for the LDS tile", N);
