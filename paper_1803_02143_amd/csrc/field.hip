@@ -37,6 +37,8 @@ AxisGrid axis_grid(int degree, int64_t n, double lo, double len) {
 
 namespace {
 
+constexpr int kU = 8;  // loads issued back to back per thread
+
 __device__ __forceinline__ double node_coord(const AxisGrid& g, int64_t c) {
     const int64_t cell = c / g.m;
     return g.lo + (static_cast<double>(cell) + g.xi[c - cell * g.m]) * g.h;
@@ -105,29 +107,39 @@ velocity_reduce(const T* __restrict__ f, int n3, int n4, AxisGrid g3,
 
     const int64_t b = blockIdx.x;
     const T* __restrict__ blk = f + b * static_cast<int64_t>(n3) * n4;
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int total = n3 * n4;
+    // element e = c*n4 + d; (c, d) advance by kRedBlock elements per round
+    const int step_c = kRedBlock / n4;
+    const int step_d = kRedBlock - step_c * n4;
+    int c = threadIdx.x / n4;
+    int d = threadIdx.x - c * n4;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int c = wv; c < n3; c += kRedBlock / 64) {
-        const T* __restrict__ row = blk + static_cast<int64_t>(c) * n4;
-        double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
-        for (int e = lane; e < n4; e += 64) {
-            const double x = static_cast<double>(row[e]);
-            const double we = wt4[e];
-            r0 = fma(we, x, r0);
-            if (DIAG) {
-                r1 = fma(we, fabs(x), r1);
-                r2 = fma(we * x, x, r2);
-                r3 = fma(we * x, vq4[e], r3);
+    for (int e = threadIdx.x; e < total; e += kU * kRedBlock) {
+        T x[kU];
+        int cc[kU], dd[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const bool ok = e + u * kRedBlock < total;
+            x[u] = ok ? blk[e + u * kRedBlock] : T(0);
+            cc[u] = ok ? c : 0;
+            dd[u] = ok ? d : 0;
+            c += step_c;
+            d += step_d;
+            if (d >= n4) {
+                d -= n4;
+                ++c;
             }
         }
-        const double wc = wt3[c];
-        acc[0] = fma(wc, r0, acc[0]);
-        if (DIAG) {
-            acc[1] = fma(wc, r1, acc[1]);
-            acc[2] = fma(wc, r2, acc[2]);
-            // sum W (v1^2 + v2^2) f = v1^2 * sum W f + sum W v2^2 f
-            acc[3] = fma(wc, fma(vq3[c], r0, r3), acc[3]);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const double xv = static_cast<double>(x[u]);
+            const double wv = wt3[cc[u]] * wt4[dd[u]];
+            acc[0] = fma(wv, xv, acc[0]);
+            if (DIAG) {
+                acc[1] = fma(wv, fabs(xv), acc[1]);
+                acc[2] = fma(wv * xv, xv, acc[2]);
+                acc[3] = fma(wv * xv, vq3[cc[u]] + vq4[dd[u]], acc[3]);
+            }
         }
     }
     if (DIAG) {
@@ -151,11 +163,21 @@ moments_final(const double* __restrict__ part, int n1, int n2, AxisGrid g1,
     __shared__ double red[4 * (kRedBlock / 64)];
     const int64_t nblk = static_cast<int64_t>(n1) * n2;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t q = threadIdx.x; q < nblk; q += kRedBlock) {
-        const int64_t a = q / n2;
-        const double w = node_weight(g1, a) * node_weight(g2, q - a * n2);
+    for (int64_t q0 = threadIdx.x; q0 < nblk; q0 += kU * kRedBlock) {
+        double x[kU][4], w[kU];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) acc[k] = fma(w, part[k * nblk + q], acc[k]);
+        for (int u = 0; u < kU; ++u) {
+            const int64_t q = q0 + u * kRedBlock;
+            const bool ok = q < nblk;
+            const int64_t a = q / n2;
+            w[u] = ok ? node_weight(g1, a) * node_weight(g2, q - a * n2) : 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) x[u][k] = ok ? part[k * nblk + q] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] = fma(w[u], x[u][k], acc[k]);
     }
     block_sum<4>(acc, red);
     if (threadIdx.x == 0) {

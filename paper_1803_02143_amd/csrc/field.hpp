@@ -44,5 +44,10 @@ vp_status moments_final_impl(int degree, const int64_t dims[4],
 vp_status poisson_impl(int degree, int64_t n1, int64_t n2, double L1, double L2,
                        const double* rho, double* E1, double* E2, double* W_el,
                        void* workspace, hipStream_t st);
+// As poisson_impl, and also writes sig1 = s1*E1, sig2 = s2*E2 when sig1 != NULL.
+vp_status poisson_impl_shift(int degree, int64_t n1, int64_t n2, double L1, double L2,
+                             const double* rho, double* E1, double* E2, double* W_el,
+                             void* workspace, double* sig1, double* sig2, double s1,
+                             double s2, hipStream_t st);
 
 }  // namespace vp

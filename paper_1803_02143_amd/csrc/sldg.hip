@@ -26,6 +26,7 @@ namespace vp {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kU = 8;  // loads issued back to back per thread
 
 template <int M>
 __device__ __forceinline__ void lagrange_all(const NodeBasis& b, double t,
@@ -183,7 +184,18 @@ sldg_row(const T* __restrict__ fin, T* __restrict__ fout,
     }
     const int64_t base = row0 * N;
     const int cnt = nr * N;
-    for (int e = threadIdx.x; e < cnt; e += kBlock) tile[e] = fin[base + e];
+    {
+        // batches of kU independent loads keep many requests in flight
+        int e = threadIdx.x;
+        for (; e + (kU - 1) * kBlock < cnt; e += kU * kBlock) {
+            T v[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) v[u] = fin[base + e + u * kBlock];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) tile[e + u * kBlock] = v[u];
+        }
+        for (; e < cnt; e += kBlock) tile[e] = fin[base + e];
+    }
     __syncthreads();
 
     const int ncell = nr * nc;

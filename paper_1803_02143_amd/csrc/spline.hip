@@ -29,6 +29,7 @@ namespace vp {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kU = 8;  // loads issued back to back per thread
 
 template <typename T>
 struct SplineParams {
@@ -124,8 +125,18 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout,
     const int lane = threadIdx.x % L;
     const int row_step = kBlock / L;
     if (lane < nl) {
-        for (int i = threadIdx.x / L; i < n; i += row_step)
-            buf[i * L + lane] = fin[base + i * inner + lane];
+        // batches of kU independent loads keep many requests in flight
+        int i = threadIdx.x / L;
+        for (; i + (kU - 1) * row_step < n; i += kU * row_step) {
+            T v[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                v[u] = fin[base + static_cast<int64_t>(i + u * row_step) * inner + lane];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) buf[(i + u * row_step) * L + lane] = v[u];
+        }
+        for (; i < n; i += row_step)
+            buf[i * L + lane] = fin[base + static_cast<int64_t>(i) * inner + lane];
     }
     __syncthreads();
     if (threadIdx.x < nl) {
@@ -173,9 +184,25 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout,
     const int nr = static_cast<int>(min(static_cast<int64_t>(R), nrows - row0));
     const int64_t base = row0 * n;
     const int cnt = nr * n;
-    for (int e = threadIdx.x; e < cnt; e += kBlock) {
-        const int r = e / n;
-        buf[r * ld + (e - r * n)] = fin[base + e];
+    // row of element e: exact for e < 2^16 with the rounded reciprocal
+    const float inv_n = 1.0f / static_cast<float>(n);
+    {
+        int e = threadIdx.x;
+        for (; e + (kU - 1) * kBlock < cnt; e += kU * kBlock) {
+            T v[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) v[u] = fin[base + e + u * kBlock];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int q = e + u * kBlock;
+                const int r = static_cast<int>((static_cast<float>(q) + 0.5f) * inv_n);
+                buf[r * ld + (q - r * n)] = v[u];
+            }
+        }
+        for (; e < cnt; e += kBlock) {
+            const int r = static_cast<int>((static_cast<float>(e) + 0.5f) * inv_n);
+            buf[r * ld + (e - r * n)] = fin[base + e];
+        }
     }
     __syncthreads();
     if (threadIdx.x < nr) {
@@ -192,7 +219,7 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout,
     }
     __syncthreads();
     for (int e = threadIdx.x; e < cnt; e += kBlock) {
-        const int r = e / n;
+        const int r = static_cast<int>((static_cast<float>(e) + 0.5f) * inv_n);
         const int i = e - r * n;
         const T* row = buf + r * ld;
         const T* w = wts + 4 * r;

@@ -35,16 +35,6 @@ struct vp_state {
 namespace vp {
 namespace {
 
-__global__ void scale2(const double* __restrict__ a, const double* __restrict__ b,
-                       double sa, double sb, double* __restrict__ oa,
-                       double* __restrict__ ob, int64_t n) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) {
-        oa[i] = sa * a[i];
-        ob[i] = sb * b[i];
-    }
-}
-
 __global__ void xshift(const double* __restrict__ v1, const double* __restrict__ v2,
                        int64_t n3, int64_t n4, double s1, double s2,
                        double* __restrict__ o1, double* __restrict__ o2) {
@@ -230,7 +220,6 @@ extern "C" vp_status vp_strang_step(vp_state* st, void* f, void* f_tmp, int nste
         return set_error(VP_ERR_ARG, "state belongs to device %d, current device is %d",
                          st->device, cur);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t nx = st->dims[0] * st->dims[1];
     vp_status rc = VP_OK;
 
     // x-sweep shifts: (tau/2) v / h_x, one value per velocity node
@@ -251,14 +240,13 @@ extern "C" vp_status vp_strang_step(vp_state* st, void* f, void* f_tmp, int nste
         mark(st, VP_TIMER_FIELD, s);
         rc = density_impl(st->degree, st->dt, st->dims, f, st->len[2], st->len[3],
                           st->rho, s);
+        // E of the half-step state and the v-sweep shifts tau E_d / h_{v_d}
         if (rc == VP_OK)
-            rc = poisson_impl(st->degree, st->dims[0], st->dims[1], st->len[0],
-                              st->len[1], st->rho, st->e1, st->e2, nullptr, st->pws, s);
+            rc = poisson_impl_shift(st->degree, st->dims[0], st->dims[1], st->len[0],
+                                    st->len[1], st->rho, st->e1, st->e2, nullptr, st->pws,
+                                    st->sig_v1, st->sig_v2, tau / st->h[2],
+                                    tau / st->h[3], s);
         if (rc != VP_OK) return rc;
-        scale2<<<blocks_for(nx, 256), 256, 0, s>>>(st->e1, st->e2, tau / st->h[2],
-                                                   tau / st->h[3], st->sig_v1,
-                                                   st->sig_v2, nx);
-        if ((rc = check_launch("scale2")) != VP_OK) return rc;
         mark(st, VP_TIMER_FIELD, s);
         if ((rc = sweep(st, 2, f, f_tmp, st->sig_v1, s)) != VP_OK) return rc;
         if ((rc = sweep(st, 3, f_tmp, f, st->sig_v2, s)) != VP_OK) return rc;

@@ -82,7 +82,7 @@ def test_spline_and_field_argument_errors():
     assert lib.vp_density(-2, L.VP_F64, dims, pa, 1.0, 1.0, pb, None) == L.VP_ERR_UNSUPPORTED
     assert lib.vp_density(2, L.VP_F64, dims, pa, -1.0, 1.0, pb, None) == L.VP_ERR_ARG
     ws = lib.vp_poisson_workspace(2, 6, 6)
-    assert ws >= 4 * 16 * 36
+    assert ws >= 3 * 16 * 36
     assert lib.vp_poisson(2, 6, 6, 1.0, 1.0, pa, pb, pb, None, pa, ws, None) == L.VP_ERR_ALIAS
     c = _fake()
     pc = ctypes.cast(c, ctypes.c_void_p)
