@@ -60,38 +60,60 @@ __device__ __forceinline__ void spline_weights(double sigma, int n, int& s,
     wq[3] = T(g * b3);
 }
 
-// In-place periodic solve on one line: element i at p[i * stride].
+// Segmented in-place periodic solve, called by every thread of the block.
+// The thread owning segment [b, e) of the line at p (element i at
+// p[i * stride]) starts each recursion from the truncated periodic sum of its
+// predecessors (causal) or successors (anti-causal), so the Q segments of a
+// line run in parallel:
+//   y_{b-1} = inv_geo sum_{k<K} r^k u_{b-1-k},  y_i = u_i + r y_{i-1};
+//   w_e     = inv_geo sum_{k<K} r^k y_{e+k},    w_i = y_i + r w_{i+1}
+// (indices mod n).  With K = n the start values are the exact periodic sums.
 template <typename T>
-__device__ __forceinline__ void spline_solve_line(T* p, int stride,
-                                                  const SplineParams<T>& sp) {
+__device__ __forceinline__ void spline_solve_segment(T* p, int stride, int b, int e,
+                                                     bool active,
+                                                     const SplineParams<T>& sp) {
     const int n = sp.n;
     const T r = sp.r;
-    // causal: y_0 = inv_geo * sum_{k<K} r^k u_{(n-k) mod n}
-    T acc = p[0];
-    T rk = r;
-    for (int k = 1; k < sp.K; ++k) {
-        acc = fma(rk, p[(n - k) * stride], acc);
-        rk *= r;
+    T y = T(0);
+    if (active) {
+        T acc = T(0), rk = T(1);
+        int j = b - 1;
+        if (j < 0) j += n;
+        for (int k = 0; k < sp.K; ++k) {
+            acc = fma(rk, p[j * stride], acc);
+            rk *= r;
+            if (--j < 0) j += n;
+        }
+        y = acc * sp.inv_geo;
     }
-    T y = acc * sp.inv_geo;
-    p[0] = y;
-    for (int i = 1; i < n; ++i) {
-        y = fma(r, y, p[i * stride]);
-        p[i * stride] = y;
+    __syncthreads();
+    if (active) {
+        for (int i = b; i < e; ++i) {
+            y = fma(r, y, p[i * stride]);
+            p[i * stride] = y;
+        }
     }
-    // anti-causal: w_{n-1} = inv_geo * sum_{k<K} r^k y_{(n-1+k) mod n}
-    acc = p[(n - 1) * stride];
-    rk = r;
-    for (int k = 1; k < sp.K; ++k) {
-        acc = fma(rk, p[(k - 1) * stride], acc);
-        rk *= r;
+    __syncthreads();
+    T w = T(0);
+    if (active) {
+        T acc = T(0), rk = T(1);
+        int j = e;
+        if (j >= n) j -= n;
+        for (int k = 0; k < sp.K; ++k) {
+            acc = fma(rk, p[j * stride], acc);
+            rk *= r;
+            if (++j >= n) j -= n;
+        }
+        w = acc * sp.inv_geo;
     }
-    T w = acc * sp.inv_geo;
-    p[(n - 1) * stride] = w;
-    for (int i = n - 2; i >= 0; --i) {
-        w = fma(r, w, p[i * stride]);
-        p[i * stride] = w;
+    __syncthreads();
+    if (active) {
+        for (int i = e - 1; i >= b; --i) {
+            w = fma(r, w, p[i * stride]);
+            p[i * stride] = w;
+        }
     }
+    __syncthreads();
 }
 
 __device__ __forceinline__ int wrap(int j, int n) {
@@ -106,6 +128,9 @@ __device__ __forceinline__ int first_tap(int i, int s, int n) {
     return j;
 }
 
+// Lines along a strided axis.  Thread t owns line l = t % L (L adjacent
+// lines of the fastest axis) and segment q = t / L of that line, for the
+// load, the solve and the evaluation alike.
 template <typename T, int AXIS>
 __global__ void __launch_bounds__(kBlock)
 spline_col(const T* __restrict__ fin, T* __restrict__ fout,
@@ -114,60 +139,72 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout,
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = sp.n;
     T* buf = reinterpret_cast<T*>(smem);   // [n][L]
-    T* wts = buf + n * L;                  // [L][4]
-    int* sh = reinterpret_cast<int*>(wts + 4 * L);
 
     const int64_t o = blockIdx.x / tiles_per_outer;
     const int64_t k0 = (blockIdx.x - o * tiles_per_outer) * L;
     const int nl = static_cast<int>(min(static_cast<int64_t>(L), inner - k0));
     const int64_t base = o * n * inner + k0;
 
-    const int lane = threadIdx.x % L;
-    const int row_step = kBlock / L;
-    if (lane < nl) {
+    const int l = threadIdx.x % L;
+    const int Q = kBlock / L;
+    const int S = (n + Q - 1) / Q;
+    const int b = min(n, (static_cast<int>(threadIdx.x) / L) * S);
+    const int e = min(n, b + S);
+    const bool active = l < nl && b < e;
+    const T* __restrict__ src = fin + base + l;
+    T* __restrict__ dst = fout + base + l;
+    if (active) {
         // batches of kU independent loads keep many requests in flight
-        int i = threadIdx.x / L;
-        for (; i + (kU - 1) * row_step < n; i += kU * row_step) {
+        int i = b;
+        for (; i + kU <= e; i += kU) {
             T v[kU];
 #pragma unroll
-            for (int u = 0; u < kU; ++u)
-                v[u] = fin[base + static_cast<int64_t>(i + u * row_step) * inner + lane];
+            for (int u = 0; u < kU; ++u) v[u] = src[static_cast<int64_t>(i + u) * inner];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) buf[(i + u * row_step) * L + lane] = v[u];
+            for (int u = 0; u < kU; ++u) buf[(i + u) * L + l] = v[u];
         }
-        for (; i < n; i += row_step)
-            buf[i * L + lane] = fin[base + static_cast<int64_t>(i) * inner + lane];
+        for (; i < e; ++i) buf[i * L + l] = src[static_cast<int64_t>(i) * inner];
     }
-    __syncthreads();
-    if (threadIdx.x < nl) {
-        const int l = threadIdx.x;
-        int s;
+    int s = 0;
+    T w0 = T(0), w1 = T(0), w2 = T(0), w3 = T(0);
+    if (active) {
         T wq[4];
         spline_weights<T>(shift[shift_offset(sm, o, k0 + l)], n, s, wq);
-        wts[4 * l + 0] = wq[0];
-        wts[4 * l + 1] = wq[1];
-        wts[4 * l + 2] = wq[2];
-        wts[4 * l + 3] = wq[3];
-        sh[l] = s;
-        spline_solve_line<T>(buf + l, L, sp);
+        w0 = wq[0];
+        w1 = wq[1];
+        w2 = wq[2];
+        w3 = wq[3];
     }
     __syncthreads();
-    if (lane < nl) {
-        const T w0 = wts[4 * lane + 0], w1 = wts[4 * lane + 1];
-        const T w2 = wts[4 * lane + 2], w3 = wts[4 * lane + 3];
-        const int s = sh[lane];
-        for (int i = threadIdx.x / L; i < n; i += row_step) {
-            const int j0 = first_tap(i, s, n);
-            const int j1 = wrap(j0 + 1, n), j2 = wrap(j0 + 2, n), j3 = wrap(j0 + 3, n);
-            T acc = w0 * buf[j0 * L + lane];
-            acc = fma(w1, buf[j1 * L + lane], acc);
-            acc = fma(w2, buf[j2 * L + lane], acc);
-            acc = fma(w3, buf[j3 * L + lane], acc);
-            fout[base + i * inner + lane] = acc;
+    spline_solve_segment<T>(buf + l, L, b, e, active, sp);
+    if (active) {
+        // sliding window over omega_{i-s-2 .. i-s+1}
+        int j = first_tap(b, s, n);
+        T c0 = buf[j * L + l];
+        j = wrap(j + 1, n);
+        T c1 = buf[j * L + l];
+        j = wrap(j + 1, n);
+        T c2 = buf[j * L + l];
+        j = wrap(j + 1, n);
+        T c3 = buf[j * L + l];
+        for (int i = b; i < e; ++i) {
+            T acc = w0 * c0;
+            acc = fma(w1, c1, acc);
+            acc = fma(w2, c2, acc);
+            acc = fma(w3, c3, acc);
+            dst[static_cast<int64_t>(i) * inner] = acc;
+            c0 = c1;
+            c1 = c2;
+            c2 = c3;
+            j = wrap(j + 1, n);
+            c3 = buf[j * L + l];
         }
     }
 }
 
+// Lines along the contiguous axis.  Loads and stores are element-parallel
+// (consecutive threads, consecutive addresses); the solve gives thread t
+// row r = t % R and segment q = t / R.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 spline_row(const T* __restrict__ fin, T* __restrict__ fout,
@@ -204,7 +241,6 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout,
             buf[r * ld + (e - r * n)] = fin[base + e];
         }
     }
-    __syncthreads();
     if (threadIdx.x < nr) {
         const int r = threadIdx.x;
         int s;
@@ -215,9 +251,16 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout,
         wts[4 * r + 2] = wq[2];
         wts[4 * r + 3] = wq[3];
         sh[r] = s;
-        spline_solve_line<T>(buf + r * ld, 1, sp);
     }
     __syncthreads();
+    {
+        const int r = threadIdx.x % R;
+        const int Q = kBlock / R;
+        const int S = (n + Q - 1) / Q;
+        const int b = min(n, (static_cast<int>(threadIdx.x) / R) * S);
+        const int e = min(n, b + S);
+        spline_solve_segment<T>(buf + r * ld, 1, b, e, r < nr && b < e, sp);
+    }
     for (int e = threadIdx.x; e < cnt; e += kBlock) {
         const int r = static_cast<int>((static_cast<float>(e) + 0.5f) * inv_n);
         const int i = e - r * n;
@@ -239,8 +282,8 @@ SplineParams<T> make_params(int n) {
     sp.r = T(r);
     sp.inv_geo = T(1.0 / (1.0 - std::pow(r, n)));
     sp.n = n;
-    // |r|^K below the rounding unit: K = 40 (double), 20 (float)
-    const int kmax = sizeof(T) == 8 ? 40 : 20;
+    // |r|^K / (1 - |r|) below the rounding unit: K = 28 (double), 14 (float)
+    const int kmax = sizeof(T) == 8 ? 28 : 14;
     sp.K = n < kmax ? n : kmax;
     return sp;
 }
@@ -259,12 +302,14 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
     const T* in = static_cast<const T*>(fin);
     T* out = static_cast<T*>(fout);
     if (axis < 3) {
+        // lines per tile: a power of two dividing the fastest block when one
+        // of at least 16 does, within the LDS budget
         int L = 64;
-        while (L > 1 && (static_cast<size_t>(n) * L * sizeof(T) > kTileBytes ||
-                         L / 2 >= inner))
+        while (L > 16 && inner % L) L /= 2;
+        if (inner % L) L = 64;
+        while (L > 1 && (static_cast<size_t>(n) * L * sizeof(T) > kTileBytes || L / 2 >= inner))
             L /= 2;
-        const size_t lds = static_cast<size_t>(n) * L * sizeof(T) +
-                           static_cast<size_t>(L) * (4 * sizeof(T) + sizeof(int));
+        const size_t lds = static_cast<size_t>(n) * L * sizeof(T);
         if (lds > 64 * 1024)
             return set_error(VP_ERR_UNSUPPORTED,
                              "spline_advect: line of %d points too long for the LDS tile", n);
