@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--dtype", default=None, help="f64 or f32 (default: the config's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--methods", default="sldg,spline")
+    ap.add_argument("--copy-ref", type=int, default=0,
+                    help="plain device copies of one f buffer before the run (a "
+                         "reference kernel of known size for hardware counters)")
     return ap.parse_args()
 
 
@@ -109,6 +112,10 @@ def main():
         vp.vp_init(vp.IC_LANDAU if w.ic == "landau" else vp.IC_TWO_STREAM_SUM,
                    w.eps, w.k, w.v0, deg, f, w.lo, w.length)
         runs.append({"name": m, "st": st, "f": f, "tmp": tmp})
+
+    for _ in range(a.copy_ref):
+        runs[0]["tmp"].copy_(runs[0]["f"])
+    torch.cuda.synchronize()
 
     # warm-up, then the timed region: each solver advances `steps` Strang
     # steps in one call, recording W and the moments of every state
