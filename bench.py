@@ -44,6 +44,34 @@ def parse():
     return ap.parse_args()
 
 
+def counter_traffic(kernel_key, workload_name, dtype):
+    """HBM bytes per launch of one sweep kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, or None when no summary covers it or the
+    kernel sources changed since the counters were taken."""
+    import glob
+    import hashlib
+    import re
+
+    csrc = os.path.join(ROOT, "paper_1803_02143_amd", "csrc")
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm_counters.md"))):
+        m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+        if not m:
+            continue
+        data = json.loads(m.group(1))
+        if data.get("workload") != workload_name or data.get("dtype") != dtype:
+            continue
+        entry = data["per_launch"].get(kernel_key)
+        if entry is None:
+            return None
+        src = "sldg.hip" if kernel_key.startswith("sldg") else "spline.hip"
+        for f in (src, "vp4d_internal.hpp"):
+            h = hashlib.sha256(open(os.path.join(csrc, f), "rb").read()).hexdigest()[:16]
+            if data["sources"].get(f) != h:
+                return None
+        return entry["read_bytes"] + entry["written_bytes"]
+    return None
+
+
 def cpu_baseline(w, dtype):
     """The oracle's sweep rate on a bounded sample: one SLDG and one spline
     sweep along every axis of the full grid, shifts of the step's shape."""
@@ -158,7 +186,7 @@ def main():
     dom = detail[dominant]
     roofline = {"kernel": dominant, "bound": "hbm", "achieved": dom["alg_GBs"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["alg_GBs"] / HBM_PEAK_GBS,
-                "traffic": None,
+                "traffic": counter_traffic(dominant, w.name, dt),
                 "alg_bytes_per_launch": 2 * n4 * esize}
     W_last = {r["name"]: float(r["W"][-1].item()) for r in runs}
     mass_drift = {r["name"]: float(((r["mom"][0::4] - r["mom"][0]).abs().max() / r["mom"][0]).item())
