@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--config", default="landau_32")
     ap.add_argument("--dtype", default=None, help="f64 or f32 (default: the config's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-precision", action="store_true",
+                    help="skip the second timed run in the other storage precision")
     ap.add_argument("--methods", default="sldg,spline")
     ap.add_argument("--copy-ref", type=int, default=0,
                     help="plain device copies of one f buffer before the run (a "
@@ -107,29 +109,11 @@ def cpu_baseline(w, dtype):
                       f"float64, 1 thread, {dt:.1f} s"}
 
 
-def main():
-    a = parse()
-    if a.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the "
-              "multi-GPU sharding is described in DESIGN.md", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    import paper_1803_02143_amd as vp
-    from vp_inputs import workload
-
-    w = workload(a.config)
-    dt = a.dtype or w.dtype
+def run_precision(vp, torch, w, dt, methods, steps, warmup, stream, copy_ref=0):
+    """Init, warm up and time `steps` Strang steps of every method in one
+    precision; returns the timed seconds and the per-method runs."""
     tdt = torch.float64 if dt == "f64" else torch.float32
-    esize = 8 if dt == "f64" else 4
     dims = w.dofs
-    n4 = int(np.prod(dims))
-    methods = [m for m in a.methods.split(",") if m]
-    torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
-
     runs = []
     for m in methods:
         method = vp.METHOD_SLDG if m == "sldg" else vp.METHOD_SPLINE
@@ -141,33 +125,37 @@ def main():
                    w.eps, w.k, w.v0, deg, f, w.lo, w.length)
         runs.append({"name": m, "st": st, "f": f, "tmp": tmp})
 
-    for _ in range(a.copy_ref):
+    for _ in range(copy_ref):
         runs[0]["tmp"].copy_(runs[0]["f"])
     torch.cuda.synchronize()
 
     # warm-up, then the timed region: each solver advances `steps` Strang
     # steps in one call, recording W and the moments of every state
     for r in runs:
-        if a.warmup:
-            r["st"].step(r["f"], r["tmp"], a.warmup, w.dt, None, None, stream)
-        r["W"] = torch.empty(a.steps + 1, dtype=torch.float64, device="cuda")
-        r["mom"] = torch.empty(4 * (a.steps + 1), dtype=torch.float64, device="cuda")
+        if warmup:
+            r["st"].step(r["f"], r["tmp"], warmup, w.dt, None, None, stream)
+        r["W"] = torch.empty(steps + 1, dtype=torch.float64, device="cuda")
+        r["mom"] = torch.empty(4 * (steps + 1), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     for r in runs:
         r["st"].timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for r in runs:
-        r["st"].step(r["f"], r["tmp"], a.steps, w.dt, r["W"], r["mom"], stream)
+        r["st"].step(r["f"], r["tmp"], steps, w.dt, r["W"], r["mom"], stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     for r in runs:
         r["timers"] = r["st"].timing_read()
         r["st"].timing_enable(False)
+        r["st"].close()
+        del r["tmp"]
+    return elapsed, runs
 
-    sweeps = SWEEPS_PER_STEP * len(runs)
-    value = sweeps * n4 * a.steps / elapsed
-    # per-kernel averages from the HIP events
+
+def kernel_table(runs, n4, esize):
+    """Per-kernel averages from the library's HIP events, and the sweep with
+    the largest total time."""
     detail = {}
     dominant = None
     for r in runs:
@@ -183,6 +171,36 @@ def main():
             detail[key] = d
             if name.startswith("sweep") and (dominant is None or ms > detail[dominant]["total_ms"]):
                 dominant = key
+    return detail, dominant
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the "
+              "multi-GPU sharding is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1803_02143_amd as vp
+    from vp_inputs import workload
+
+    w = workload(a.config)
+    dt = a.dtype or w.dtype
+    esize = 8 if dt == "f64" else 4
+    dims = w.dofs
+    n4 = int(np.prod(dims))
+    methods = [m for m in a.methods.split(",") if m]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    elapsed, runs = run_precision(vp, torch, w, dt, methods, a.steps, a.warmup, stream,
+                                  a.copy_ref)
+    sweeps = SWEEPS_PER_STEP * len(runs)
+    value = sweeps * n4 * a.steps / elapsed
+    detail, dominant = kernel_table(runs, n4, esize)
     dom = detail[dominant]
     roofline = {"kernel": dominant, "bound": "hbm", "achieved": dom["alg_GBs"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["alg_GBs"] / HBM_PEAK_GBS,
@@ -214,10 +232,32 @@ def main():
         "W_el_last": W_last,
         "rel_mass_drift": mass_drift,
     }
+
+    if not a.no_other_precision:
+        # the same steps in the other storage precision: its rates, and its
+        # difference from this run (which matches the FP64 oracle to 1e-12)
+        odt = "f32" if dt == "f64" else "f64"
+        oes = 8 if odt == "f64" else 4
+        oel, oruns = run_precision(vp, torch, w, odt, methods, a.steps, a.warmup, stream)
+        odetail, _ = kernel_table(oruns, n4, oes)
+        diffs = {}
+        for r, q in zip(runs, oruns):
+            fa = r["f"].double()
+            fb = q["f"].double()
+            diffs[r["name"]] = {
+                "rel_l2_f": float((fb - fa).norm() / fa.norm()),
+                "rel_max_W": float(((q["W"] - r["W"]).abs() / r["W"].abs()).max()),
+            }
+        out["other_precision"] = {
+            "dtype": odt, "ms_per_step": oel / a.steps * 1e3,
+            "value": sweeps * n4 * a.steps / oel,
+            "speedup_vs_main": elapsed / oel,
+            "difference_vs_main_after_run": diffs,
+            "kernels": {k: {kk: v[kk] for kk in ("avg_ms", "dof_updates_per_s", "alg_GBs") if kk in v}
+                        for k, v in odetail.items()},
+        }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, dt)
-    for r in runs:
-        r["st"].close()
     print(json.dumps(out))
 
 

@@ -47,9 +47,8 @@ def cell_width(length, n_dofs, degree):
 
 # ---------------------------------------------------- initial conditions ---
 
-def initial_condition(kind, dims, lo, length, degree, eps, k, v0=0.0,
-                      form="sum"):
-    """Sample f0 at the nodes (the dofs are point values, Sec. 3).
+def initial_condition_at(kind, x1, x2, v1, v2, eps, k, v0=0.0, form="sum"):
+    """f0 at coordinate arrays that broadcast against each other.
 
     landau:     (2 pi)^-1 exp(-(v1^2+v2^2)/2) (1 + eps (cos k x1 + cos k x2))
                 (Sec. 4, Eq. (6)).
@@ -58,23 +57,30 @@ def initial_condition(kind, dims, lo, length, degree, eps, k, v0=0.0,
                 cos k x2 for form="product", 1 + eps (cos k x1 + cos k x2)
                 for form="sum".
     """
-    x1, x2, v1, v2 = (nodes_1d(lo[d], length[d], dims[d], degree)
-                      for d in range(4))
     if kind == "landau":
-        px = 1.0 + eps * (np.cos(k * x1)[:, None] + np.cos(k * x2)[None, :])
-        fv = np.exp(-0.5 * v1 ** 2)[:, None] * np.exp(-0.5 * v2 ** 2)[None, :]
-        fv = fv / (2.0 * np.pi)
+        px = 1.0 + eps * (np.cos(k * x1) + np.cos(k * x2))
+        fv = np.exp(-0.5 * v1 ** 2) * np.exp(-0.5 * v2 ** 2) / (2.0 * np.pi)
     elif kind == "two_stream":
         if form == "product":
-            px = 1.0 + eps * np.cos(k * x1)[:, None] * np.cos(k * x2)[None, :]
+            px = 1.0 + eps * np.cos(k * x1) * np.cos(k * x2)
         else:
-            px = 1.0 + eps * (np.cos(k * x1)[:, None] + np.cos(k * x2)[None, :])
+            px = 1.0 + eps * (np.cos(k * x1) + np.cos(k * x2))
         g1 = np.exp(-0.5 * (v1 - v0) ** 2) + np.exp(-0.5 * (v1 + v0) ** 2)
         g2 = np.exp(-0.5 * (v2 - v0) ** 2) + np.exp(-0.5 * (v2 + v0) ** 2)
-        fv = g1[:, None] * g2[None, :] / (8.0 * np.pi)
+        fv = g1 * g2 / (8.0 * np.pi)
     else:
         raise ValueError(kind)
-    return px[:, :, None, None] * fv[None, None, :, :]
+    return px * fv
+
+
+def initial_condition(kind, dims, lo, length, degree, eps, k, v0=0.0,
+                      form="sum"):
+    """Sample f0 at the nodes (the dofs are point values, Sec. 3)."""
+    x1, x2, v1, v2 = (nodes_1d(lo[d], length[d], dims[d], degree)
+                      for d in range(4))
+    return initial_condition_at(kind, x1[:, None, None, None], x2[None, :, None, None],
+                                v1[None, None, :, None], v2[None, None, None, :],
+                                eps, k, v0, form)
 
 
 # ---------------------------------------------------------------- density ---

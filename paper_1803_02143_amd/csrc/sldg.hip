@@ -42,30 +42,16 @@ __device__ __forceinline__ void lagrange_all(const NodeBasis& b, double t,
 }
 
 // Builds the line operator.  alpha == 0 gives A = 0, B = I exactly, so a
-// whole-cell shift is an exact permutation of the cells.
+// whole-cell shift is an exact permutation of the cells; a shift that
+// split_shift rejects gives NaN entries.  (Branch-free selects keep A and B
+// in registers.)
 template <int M, typename T>
 __device__ __forceinline__ void sldg_operator(const NodeBasis& b, double sigma,
                                               int nc, int& s, T A[M][M],
                                               T B[M][M]) {
     double alpha;
-    if (!split_shift(sigma, nc, s, alpha)) {
-        const T nan = T(__builtin_nan(""));
-#pragma unroll
-        for (int j = 0; j < M; ++j)
-#pragma unroll
-            for (int l = 0; l < M; ++l) A[j][l] = B[j][l] = nan;
-        return;
-    }
-    if (alpha == 0.0) {
-#pragma unroll
-        for (int j = 0; j < M; ++j)
-#pragma unroll
-            for (int l = 0; l < M; ++l) {
-                A[j][l] = T(0);
-                B[j][l] = T(j == l ? 1 : 0);
-            }
-        return;
-    }
+    const bool ok = split_shift(sigma, nc, s, alpha);
+    const bool exact = alpha == 0.0;
     const double beta = 1.0 - alpha;
     double a[M][M], c[M][M];
 #pragma unroll
@@ -91,15 +77,35 @@ __device__ __forceinline__ void sldg_operator(const NodeBasis& b, double sigma,
             }
         }
     }
+    const double nan = __builtin_nan("");
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         const double sa = alpha * b.inv_w[j];
         const double sb = beta * b.inv_w[j];
 #pragma unroll
         for (int l = 0; l < M; ++l) {
-            A[j][l] = T(a[j][l] * sa);
-            B[j][l] = T(c[j][l] * sb);
+            const double av = exact ? 0.0 : a[j][l] * sa;
+            const double bv = exact ? (j == l ? 1.0 : 0.0) : c[j][l] * sb;
+            A[j][l] = T(ok ? av : nan);
+            B[j][l] = T(ok ? bv : nan);
         }
+    }
+}
+
+// One output cell: out_j = sum_l A_jl left_l + B_jl right_l, stored at
+// out[j * stride].
+template <int M, typename T>
+__device__ __forceinline__ void sldg_cell(const T A[M][M], const T B[M][M],
+                                          const T left[M], const T right[M],
+                                          T* __restrict__ out, int64_t stride) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        T acc = T(0);
+#pragma unroll
+        for (int l = 0; l < M; ++l) acc = fma(A[j][l], left[l], acc);
+#pragma unroll
+        for (int l = 0; l < M; ++l) acc = fma(B[j][l], right[l], acc);
+        out[j * stride] = acc;
     }
 }
 
@@ -128,8 +134,24 @@ sldg_col(const T* __restrict__ fin, T* __restrict__ fout,
         prev[l] = last[l];
     }
     int i = s;  // output cell fed by input cells (c-1, c)
-#pragma unroll 2
-    for (int c = 0; c < nc; ++c) {
+    // chunks of CU cells: all their loads are issued before the first use
+    constexpr int CU = M <= 3 ? 4 : 2;
+    int c = 0;
+    for (; c + CU <= nc - 1; c += CU) {
+        T cur[CU][M];
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+#pragma unroll
+            for (int l = 0; l < M; ++l) cur[u][l] = src[(c + u) * cs + l * inner];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            sldg_cell<M, T>(A, B, prev, cur[u], dst + i * cs, inner);
+#pragma unroll
+            for (int l = 0; l < M; ++l) prev[l] = cur[u][l];
+            if (++i == nc) i = 0;
+        }
+    }
+    for (; c < nc; ++c) {
         T cur[M];
         if (c < nc - 1) {
 #pragma unroll
@@ -138,15 +160,7 @@ sldg_col(const T* __restrict__ fin, T* __restrict__ fout,
 #pragma unroll
             for (int l = 0; l < M; ++l) cur[l] = last[l];
         }
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-            T acc = T(0);
-#pragma unroll
-            for (int l = 0; l < M; ++l) acc = fma(A[j][l], prev[l], acc);
-#pragma unroll
-            for (int l = 0; l < M; ++l) acc = fma(B[j][l], cur[l], acc);
-            dst[i * cs + j * inner] = acc;
-        }
+        sldg_cell<M, T>(A, B, prev, cur, dst + i * cs, inner);
 #pragma unroll
         for (int l = 0; l < M; ++l) prev[l] = cur[l];
         if (++i == nc) i = 0;

@@ -69,26 +69,93 @@ __device__ __forceinline__ void spline_weights(double sigma, int n, int& s,
 //   w_e     = inv_geo sum_{k<K} r^k y_{e+k},    w_i = y_i + r w_{i+1}
 // (indices mod n).  With K = n the start values are the exact periodic sums.
 template <typename T>
+__device__ __forceinline__ T geometric_sum_down(const T* p, int stride, int j, int cnt,
+                                                T r, T& rk, T acc) {
+    // acc + sum_{k<cnt} rk r^k p[(j - k) * stride], four loads in flight
+    int k = 0;
+    for (; k + 4 <= cnt; k += 4) {
+        const T x0 = p[(j - k) * stride], x1 = p[(j - k - 1) * stride];
+        const T x2 = p[(j - k - 2) * stride], x3 = p[(j - k - 3) * stride];
+        acc = fma(rk, x0, acc);
+        rk *= r;
+        acc = fma(rk, x1, acc);
+        rk *= r;
+        acc = fma(rk, x2, acc);
+        rk *= r;
+        acc = fma(rk, x3, acc);
+        rk *= r;
+    }
+    for (; k < cnt; ++k) {
+        acc = fma(rk, p[(j - k) * stride], acc);
+        rk *= r;
+    }
+    return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ T geometric_sum_up(const T* p, int stride, int j, int cnt,
+                                              T r, T& rk, T acc) {
+    // acc + sum_{k<cnt} rk r^k p[(j + k) * stride], four loads in flight
+    int k = 0;
+    for (; k + 4 <= cnt; k += 4) {
+        const T x0 = p[(j + k) * stride], x1 = p[(j + k + 1) * stride];
+        const T x2 = p[(j + k + 2) * stride], x3 = p[(j + k + 3) * stride];
+        acc = fma(rk, x0, acc);
+        rk *= r;
+        acc = fma(rk, x1, acc);
+        rk *= r;
+        acc = fma(rk, x2, acc);
+        rk *= r;
+        acc = fma(rk, x3, acc);
+        rk *= r;
+    }
+    for (; k < cnt; ++k) {
+        acc = fma(rk, p[(j + k) * stride], acc);
+        rk *= r;
+    }
+    return acc;
+}
+
+// Segmented in-place periodic solve, called by every thread of the block.
+// The thread owning segment [b, e) of the line at p (element i at
+// p[i * stride]) starts each recursion from the truncated periodic sum of its
+// predecessors (causal) or successors (anti-causal), so the Q segments of a
+// line run in parallel:
+//   y_{b-1} = inv_geo sum_{k<K} r^k u_{b-1-k},  y_i = u_i + r y_{i-1};
+//   w_e     = inv_geo sum_{k<K} r^k y_{e+k},    w_i = y_i + r w_{i+1}
+// (indices mod n).  With K = n the start values are the exact periodic sums.
+template <typename T>
 __device__ __forceinline__ void spline_solve_segment(T* p, int stride, int b, int e,
                                                      bool active,
                                                      const SplineParams<T>& sp) {
     const int n = sp.n;
+    const int K = sp.K;
     const T r = sp.r;
     T y = T(0);
     if (active) {
-        T acc = T(0), rk = T(1);
-        int j = b - 1;
-        if (j < 0) j += n;
-        for (int k = 0; k < sp.K; ++k) {
-            acc = fma(rk, p[j * stride], acc);
-            rk *= r;
-            if (--j < 0) j += n;
-        }
+        // indices b-1 down to b-K: first those >= 0, then n-1 downwards
+        T rk = T(1);
+        const int run = min(K, b);
+        T acc = geometric_sum_down<T>(p, stride, b - 1, run, r, rk, T(0));
+        acc = geometric_sum_down<T>(p, stride, n - 1, K - run, r, rk, acc);
         y = acc * sp.inv_geo;
     }
     __syncthreads();
     if (active) {
-        for (int i = b; i < e; ++i) {
+        int i = b;
+        for (; i + 4 <= e; i += 4) {
+            const T x0 = p[i * stride], x1 = p[(i + 1) * stride];
+            const T x2 = p[(i + 2) * stride], x3 = p[(i + 3) * stride];
+            y = fma(r, y, x0);
+            p[i * stride] = y;
+            y = fma(r, y, x1);
+            p[(i + 1) * stride] = y;
+            y = fma(r, y, x2);
+            p[(i + 2) * stride] = y;
+            y = fma(r, y, x3);
+            p[(i + 3) * stride] = y;
+        }
+        for (; i < e; ++i) {
             y = fma(r, y, p[i * stride]);
             p[i * stride] = y;
         }
@@ -96,19 +163,30 @@ __device__ __forceinline__ void spline_solve_segment(T* p, int stride, int b, in
     __syncthreads();
     T w = T(0);
     if (active) {
-        T acc = T(0), rk = T(1);
-        int j = e;
-        if (j >= n) j -= n;
-        for (int k = 0; k < sp.K; ++k) {
-            acc = fma(rk, p[j * stride], acc);
-            rk *= r;
-            if (++j >= n) j -= n;
-        }
+        // indices e up to e+K-1: first those < n, then 0 upwards
+        T rk = T(1);
+        const int start = e < n ? e : 0;
+        const int run = min(K, n - start);
+        T acc = geometric_sum_up<T>(p, stride, start, run, r, rk, T(0));
+        acc = geometric_sum_up<T>(p, stride, 0, K - run, r, rk, acc);
         w = acc * sp.inv_geo;
     }
     __syncthreads();
     if (active) {
-        for (int i = e - 1; i >= b; --i) {
+        int i = e - 1;
+        for (; i - 3 >= b; i -= 4) {
+            const T x0 = p[i * stride], x1 = p[(i - 1) * stride];
+            const T x2 = p[(i - 2) * stride], x3 = p[(i - 3) * stride];
+            w = fma(r, w, x0);
+            p[i * stride] = w;
+            w = fma(r, w, x1);
+            p[(i - 1) * stride] = w;
+            w = fma(r, w, x2);
+            p[(i - 2) * stride] = w;
+            w = fma(r, w, x3);
+            p[(i - 3) * stride] = w;
+        }
+        for (; i >= b; --i) {
             w = fma(r, w, p[i * stride]);
             p[i * stride] = w;
         }
@@ -116,15 +194,14 @@ __device__ __forceinline__ void spline_solve_segment(T* p, int stride, int b, in
     __syncthreads();
 }
 
-__device__ __forceinline__ int wrap(int j, int n) {
-    while (j >= n) j -= n;
-    return j;
-}
+// j + 1 reduced into [0, n) for j in [0, n)
+__device__ __forceinline__ int next_idx(int j, int n) { return j + 1 < n ? j + 1 : j + 1 - n; }
 
-// first index i - s - 2 reduced into [0, n)
+// first index i - s - 2 reduced into [0, n), for i, s in [0, n)
 __device__ __forceinline__ int first_tap(int i, int s, int n) {
     int j = i - s - 2;
-    while (j < 0) j += n;
+    j += j < 0 ? n : 0;
+    j += j < 0 ? n : 0;
     return j;
 }
 
@@ -181,30 +258,43 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout,
         // sliding window over omega_{i-s-2 .. i-s+1}
         int j = first_tap(b, s, n);
         T c0 = buf[j * L + l];
-        j = wrap(j + 1, n);
+        j = next_idx(j, n);
         T c1 = buf[j * L + l];
-        j = wrap(j + 1, n);
+        j = next_idx(j, n);
         T c2 = buf[j * L + l];
-        j = wrap(j + 1, n);
+        j = next_idx(j, n);
         T c3 = buf[j * L + l];
-        for (int i = b; i < e; ++i) {
-            T acc = w0 * c0;
-            acc = fma(w1, c1, acc);
-            acc = fma(w2, c2, acc);
-            acc = fma(w3, c3, acc);
-            dst[static_cast<int64_t>(i) * inner] = acc;
+        int i = b;
+        for (; i + 4 <= e; i += 4) {
+            const int j4 = next_idx(j, n), j5 = next_idx(j4, n);
+            const int j6 = next_idx(j5, n), j7 = next_idx(j6, n);
+            const T c4 = buf[j4 * L + l], c5 = buf[j5 * L + l];
+            const T c6 = buf[j6 * L + l], c7 = buf[j7 * L + l];
+            dst[static_cast<int64_t>(i) * inner] = fma(w3, c3, fma(w2, c2, fma(w1, c1, w0 * c0)));
+            dst[static_cast<int64_t>(i + 1) * inner] = fma(w3, c4, fma(w2, c3, fma(w1, c2, w0 * c1)));
+            dst[static_cast<int64_t>(i + 2) * inner] = fma(w3, c5, fma(w2, c4, fma(w1, c3, w0 * c2)));
+            dst[static_cast<int64_t>(i + 3) * inner] = fma(w3, c6, fma(w2, c5, fma(w1, c4, w0 * c3)));
+            c0 = c4;
+            c1 = c5;
+            c2 = c6;
+            c3 = c7;
+            j = j7;
+        }
+        for (; i < e; ++i) {
+            dst[static_cast<int64_t>(i) * inner] = fma(w3, c3, fma(w2, c2, fma(w1, c1, w0 * c0)));
             c0 = c1;
             c1 = c2;
             c2 = c3;
-            j = wrap(j + 1, n);
+            j = next_idx(j, n);
             c3 = buf[j * L + l];
         }
     }
 }
 
-// Lines along the contiguous axis.  Loads and stores are element-parallel
-// (consecutive threads, consecutive addresses); the solve gives thread t
-// row r = t % R and segment q = t / R.
+// Lines along the contiguous axis.  Loads and stores go row by row, one
+// wavefront per row (consecutive lanes, consecutive addresses; the row's
+// weights and shift are wavefront-uniform); the solve gives thread t row
+// r = t % R and segment q = t / R.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 spline_row(const T* __restrict__ fin, T* __restrict__ fout,
@@ -219,26 +309,33 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout,
 
     const int64_t row0 = static_cast<int64_t>(blockIdx.x) * R;
     const int nr = static_cast<int>(min(static_cast<int64_t>(R), nrows - row0));
-    const int64_t base = row0 * n;
-    const int cnt = nr * n;
-    // row of element e: exact for e < 2^16 with the rounded reciprocal
-    const float inv_n = 1.0f / static_cast<float>(n);
-    {
-        int e = threadIdx.x;
-        for (; e + (kU - 1) * kBlock < cnt; e += kU * kBlock) {
-            T v[kU];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    constexpr int kWaves = kBlock / 64;
+    // rows r = wave, wave + 4, ...; kU loads in flight per lane
+    for (int r0 = wave; r0 < nr; r0 += kWaves * kU) {
+        T v[kU];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) v[u] = fin[base + e + u * kBlock];
+        for (int u = 0; u < kU; ++u) {
+            const int r = r0 + u * kWaves;
+            if (r < nr && lane < n) v[u] = fin[(row0 + r) * n + lane];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int r = r0 + u * kWaves;
+            if (r < nr && lane < n) buf[r * ld + lane] = v[u];
+        }
+        for (int i = lane + 64; i < n; i += 64) {
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                const int q = e + u * kBlock;
-                const int r = static_cast<int>((static_cast<float>(q) + 0.5f) * inv_n);
-                buf[r * ld + (q - r * n)] = v[u];
+                const int r = r0 + u * kWaves;
+                if (r < nr) v[u] = fin[(row0 + r) * n + i];
             }
-        }
-        for (; e < cnt; e += kBlock) {
-            const int r = static_cast<int>((static_cast<float>(e) + 0.5f) * inv_n);
-            buf[r * ld + (e - r * n)] = fin[base + e];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int r = r0 + u * kWaves;
+                if (r < nr) buf[r * ld + i] = v[u];
+            }
         }
     }
     if (threadIdx.x < nr) {
@@ -261,17 +358,17 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout,
         const int e = min(n, b + S);
         spline_solve_segment<T>(buf + r * ld, 1, b, e, r < nr && b < e, sp);
     }
-    for (int e = threadIdx.x; e < cnt; e += kBlock) {
-        const int r = static_cast<int>((static_cast<float>(e) + 0.5f) * inv_n);
-        const int i = e - r * n;
+    for (int r = wave; r < nr; r += kWaves) {
         const T* row = buf + r * ld;
-        const T* w = wts + 4 * r;
-        const int j0 = first_tap(i, sh[r], n);
-        T acc = w[0] * row[j0];
-        acc = fma(w[1], row[wrap(j0 + 1, n)], acc);
-        acc = fma(w[2], row[wrap(j0 + 2, n)], acc);
-        acc = fma(w[3], row[wrap(j0 + 3, n)], acc);
-        fout[base + e] = acc;
+        const T w0 = wts[4 * r + 0], w1 = wts[4 * r + 1];
+        const T w2 = wts[4 * r + 2], w3 = wts[4 * r + 3];
+        const int s = sh[r];
+        T* __restrict__ dst = fout + (row0 + r) * n;
+        for (int i = lane; i < n; i += 64) {
+            const int j0 = first_tap(i, s, n);
+            const int j1 = next_idx(j0, n), j2 = next_idx(j1, n), j3 = next_idx(j2, n);
+            dst[i] = fma(w3, row[j3], fma(w2, row[j2], fma(w1, row[j1], w0 * row[j0])));
+        }
     }
 }
 
@@ -333,6 +430,7 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
     }
     int R = static_cast<int>(kTileBytes / ((static_cast<size_t>(n) + 1) * sizeof(T)));
     if (R > 64) R = 64;
+    if (R > 4) R &= ~3;   // whole rows per wavefront in the load and store loops
     if (R < 1)
         return set_error(VP_ERR_UNSUPPORTED,
                          "spline_advect: line of %d points too long for the LDS tile", n);
