@@ -2,12 +2,11 @@
 //
 // rho(x1, x2) = int f dv (Sec. 2) and the diagnostics of Sec. 4 (mass, L1,
 // L2, kinetic energy) are read-only reductions over the contiguous
-// (v1, v2) block that belongs to every (x1, x2) point.  One workgroup owns
-// one block: it reads the block row by row with contiguous loads, weights
-// every value with the nodal quadrature (Gauss-Legendre weights times the
-// cell width for SLDG, the spacing for the spline grid) and reduces in FP64,
-// within each 64-lane wavefront by cross-lane shuffles and across the four
-// wavefronts through LDS.  No atomics, so results are deterministic.
+// (v1, v2) block that belongs to every (x1, x2) point.  One wavefront owns
+// one block: it reads the block with contiguous loads, weights every value
+// with the nodal quadrature (Gauss-Legendre weights times the cell width for
+// SLDG, the spacing for the spline grid) and reduces in FP64 by cross-lane
+// shuffles.  No atomics, so results are deterministic.
 #include <cmath>
 
 #include "vp4d_internal.hpp"
@@ -48,36 +47,17 @@ __device__ __forceinline__ double node_weight(const AxisGrid& g, int64_t c) {
     return g.w[c % g.m] * g.h;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
+__device__ __forceinline__ double wave_sum64(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
 
-// Sums NV values over the workgroup; the result is valid in thread 0.
-template <int NV>
-__device__ __forceinline__ void block_sum(double v[NV], double* red) {
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
-    if (lane == 0)
-#pragma unroll
-        for (int q = 0; q < NV; ++q) red[wv * NV + q] = v[q];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            double s = 0.0;
-            for (int k = 0; k < kRedBlock / 64; ++k) s += red[k * NV + q];
-            v[q] = s;
-        }
-    }
-}
-
-// Per (x1,x2) block b: out[b] = sum_{c,e} W3_c W4_e f, and when DIAG also
-// out[nblk + b] = sum W |f|, out[2 nblk + b] = sum W f^2 and
-// out[3 nblk + b] = sum W (v1^2 + v2^2) f.
+// Per (x1,x2) point b: out[b] = sum_{c,e} W3_c W4_e f[b][c][e], and when DIAG
+// also out[nblk + b] = sum W |f|, out[2 nblk + b] = sum W f^2 and
+// out[3 nblk + b] = sum W (v1^2 + v2^2) f.  One wavefront per point (its
+// N3*N4 values are contiguous), kU loads in flight per lane, cross-lane
+// shuffle reduction; the weight tables are built once per workgroup.
 template <typename T, bool DIAG>
 __global__ void __launch_bounds__(kRedBlock)
 velocity_reduce(const T* __restrict__ f, int n3, int n4, AxisGrid g3,
@@ -87,7 +67,6 @@ velocity_reduce(const T* __restrict__ f, int n3, int n4, AxisGrid g3,
     double* wt4 = wt3 + n3;
     double* vq3 = wt4 + n4;              // v^2 tables, DIAG only
     double* vq4 = vq3 + (DIAG ? n3 : 0);
-    __shared__ double red[4 * (kRedBlock / 64)];
 
     for (int c = threadIdx.x; c < n3; c += kRedBlock) {
         wt3[c] = node_weight(g3, c);
@@ -105,86 +84,115 @@ velocity_reduce(const T* __restrict__ f, int n3, int n4, AxisGrid g3,
     }
     __syncthreads();
 
-    const int64_t b = blockIdx.x;
-    const T* __restrict__ blk = f + b * static_cast<int64_t>(n3) * n4;
+    constexpr int kWaves = kRedBlock / 64;
+    const int lane = threadIdx.x & 63;
     const int total = n3 * n4;
-    // element e = c*n4 + d; (c, d) advance by kRedBlock elements per round
-    const int step_c = kRedBlock / n4;
-    const int step_d = kRedBlock - step_c * n4;
-    int c = threadIdx.x / n4;
-    int d = threadIdx.x - c * n4;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int e = threadIdx.x; e < total; e += kU * kRedBlock) {
-        T x[kU];
-        int cc[kU], dd[kU];
+    // element e = c*n4 + d; (c, d) advance by 64 elements per round
+    const int step_c = 64 / n4;
+    const int step_d = 64 - step_c * n4;
+    const int c0 = lane / n4;
+    const int d0 = lane - c0 * n4;
+    for (int64_t b = static_cast<int64_t>(blockIdx.x) * kWaves + (threadIdx.x >> 6); b < nblk;
+         b += static_cast<int64_t>(gridDim.x) * kWaves) {
+        const T* __restrict__ blk = f + b * total;
+        int c = c0, d = d0;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int e = lane; e < total; e += kU * 64) {
+            T x[kU];
+            int cc[kU], dd[kU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const bool ok = e + u * kRedBlock < total;
-            x[u] = ok ? blk[e + u * kRedBlock] : T(0);
-            cc[u] = ok ? c : 0;
-            dd[u] = ok ? d : 0;
-            c += step_c;
-            d += step_d;
-            if (d >= n4) {
-                d -= n4;
-                ++c;
+            for (int u = 0; u < kU; ++u) {
+                // clamped index instead of a branch: all kU loads issue back to back
+                const bool ok = e + u * 64 < total;
+                x[u] = blk[ok ? e + u * 64 : total - 1];
+                if (!ok) x[u] = T(0);
+                cc[u] = ok ? c : 0;
+                dd[u] = ok ? d : 0;
+                c += step_c;
+                d += step_d;
+                if (d >= n4) {
+                    d -= n4;
+                    ++c;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const double xv = static_cast<double>(x[u]);
+                const double wv = wt3[cc[u]] * wt4[dd[u]];
+                acc[0] = fma(wv, xv, acc[0]);
+                if (DIAG) {
+                    acc[1] = fma(wv, fabs(xv), acc[1]);
+                    acc[2] = fma(wv * xv, xv, acc[2]);
+                    acc[3] = fma(wv * xv, vq3[cc[u]] + vq4[dd[u]], acc[3]);
+                }
             }
         }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const double xv = static_cast<double>(x[u]);
-            const double wv = wt3[cc[u]] * wt4[dd[u]];
-            acc[0] = fma(wv, xv, acc[0]);
-            if (DIAG) {
-                acc[1] = fma(wv, fabs(xv), acc[1]);
-                acc[2] = fma(wv * xv, xv, acc[2]);
-                acc[3] = fma(wv * xv, vq3[cc[u]] + vq4[dd[u]], acc[3]);
+        const double s0 = wave_sum64(acc[0]);
+        if (DIAG) {
+            const double s1 = wave_sum64(acc[1]);
+            const double s2 = wave_sum64(acc[2]);
+            const double s3 = wave_sum64(acc[3]);
+            if (lane == 0) {
+                out[b] = s0;
+                out[nblk + b] = s1;
+                out[2 * nblk + b] = s2;
+                out[3 * nblk + b] = s3;
             }
+        } else if (lane == 0) {
+            out[b] = s0;
         }
-    }
-    if (DIAG) {
-        block_sum<4>(acc, red);
-        if (threadIdx.x == 0) {
-            out[b] = acc[0];
-            out[nblk + b] = acc[1];
-            out[2 * nblk + b] = acc[2];
-            out[3 * nblk + b] = acc[3];
-        }
-    } else {
-        block_sum<1>(acc, red);
-        if (threadIdx.x == 0) out[b] = acc[0];
     }
 }
 
+constexpr int kFinalBlock = 1024;
+
 // out4 = (mass, L1, L2, kinetic) from the per-(x1,x2) partial sums.
-__global__ void __launch_bounds__(kRedBlock)
+__global__ void __launch_bounds__(kFinalBlock)
 moments_final(const double* __restrict__ part, int n1, int n2, AxisGrid g1,
               AxisGrid g2, double* __restrict__ out4) {
-    __shared__ double red[4 * (kRedBlock / 64)];
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* wt1 = reinterpret_cast<double*>(smem);
+    double* wt2 = wt1 + n1;
+    __shared__ double red[4 * (kFinalBlock / 64)];
+    for (int a = threadIdx.x; a < n1; a += kFinalBlock) wt1[a] = node_weight(g1, a);
+    for (int b = threadIdx.x; b < n2; b += kFinalBlock) wt2[b] = node_weight(g2, b);
+    __syncthreads();
     const int64_t nblk = static_cast<int64_t>(n1) * n2;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t q0 = threadIdx.x; q0 < nblk; q0 += kU * kRedBlock) {
+    for (int64_t q0 = threadIdx.x; q0 < nblk; q0 += kU * kFinalBlock) {
         double x[kU][4], w[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            const int64_t q = q0 + u * kRedBlock;
+            const int64_t q = q0 + u * kFinalBlock;
             const bool ok = q < nblk;
-            const int64_t a = q / n2;
-            w[u] = ok ? node_weight(g1, a) * node_weight(g2, q - a * n2) : 0.0;
+            const int64_t qc = ok ? q : nblk - 1;   // clamped: no branch around the loads
+            const int64_t a = qc / n2;
+            w[u] = ok ? wt1[a] * wt2[qc - a * n2] : 0.0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) x[u][k] = ok ? part[k * nblk + q] : 0.0;
+            for (int k = 0; k < 4; ++k) x[u][k] = part[k * nblk + qc];
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u)
 #pragma unroll
             for (int k = 0; k < 4; ++k) acc[k] = fma(w[u], x[u][k], acc[k]);
     }
-    block_sum<4>(acc, red);
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] = wave_sum64(acc[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) red[wv * 4 + k] = acc[k];
+    __syncthreads();
     if (threadIdx.x == 0) {
-        out4[0] = acc[0];
-        out4[1] = acc[1];
-        out4[2] = sqrt(acc[2]);
-        out4[3] = 0.5 * acc[3];
+        double t[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int i = 0; i < kFinalBlock / 64; ++i)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) t[k] += red[i * 4 + k];
+        out4[0] = t[0];
+        out4[1] = t[1];
+        out4[2] = sqrt(t[2]);
+        out4[3] = 0.5 * t[3];
     }
 }
 
@@ -240,11 +248,14 @@ vp_status launch_reduce(bool diag, const int64_t dims[4], const void* f,
     if (nblk >= (int64_t(1) << 31))
         return set_error(VP_ERR_UNSUPPORTED, "too many (x1, x2) points");
     const T* fp = static_cast<const T*>(f);
+    // one wavefront per (x1, x2) point, at most 8192 workgroups
+    int64_t grid = (nblk + kRedBlock / 64 - 1) / (kRedBlock / 64);
+    if (grid > 8192) grid = 8192;
     if (diag)
-        velocity_reduce<T, true><<<static_cast<unsigned>(nblk), kRedBlock, lds, st>>>(
+        velocity_reduce<T, true><<<static_cast<unsigned>(grid), kRedBlock, lds, st>>>(
             fp, n3, n4, g3, g4, out, nblk);
     else
-        velocity_reduce<T, false><<<static_cast<unsigned>(nblk), kRedBlock, lds, st>>>(
+        velocity_reduce<T, false><<<static_cast<unsigned>(grid), kRedBlock, lds, st>>>(
             fp, n3, n4, g3, g4, out, nblk);
     return check_launch("velocity_reduce");
 }
@@ -276,8 +287,11 @@ vp_status moments_final_impl(int degree, const int64_t dims[4],
                              hipStream_t st) {
     const AxisGrid g1 = axis_grid(degree, dims[0], lo[0], len[0]);
     const AxisGrid g2 = axis_grid(degree, dims[1], lo[1], len[1]);
-    moments_final<<<1, kRedBlock, 0, st>>>(partial, static_cast<int>(dims[0]),
-                                           static_cast<int>(dims[1]), g1, g2, out4);
+    const size_t lds = sizeof(double) * static_cast<size_t>(dims[0] + dims[1]);
+    if (lds > 48 * 1024)
+        return set_error(VP_ERR_UNSUPPORTED, "x axes too long for the moment reduction");
+    moments_final<<<1, kFinalBlock, lds, st>>>(partial, static_cast<int>(dims[0]),
+                                               static_cast<int>(dims[1]), g1, g2, out4);
     return check_launch("moments_final");
 }
 

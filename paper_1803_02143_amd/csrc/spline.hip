@@ -313,28 +313,22 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout,
     const int wave = threadIdx.x >> 6;
     constexpr int kWaves = kBlock / 64;
     // rows r = wave, wave + 4, ...; kU loads in flight per lane
+    // clamped indices instead of branches, so that the kU loads of a batch
+    // issue back to back; only the LDS stores are guarded
     for (int r0 = wave; r0 < nr; r0 += kWaves * kU) {
-        T v[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int r = r0 + u * kWaves;
-            if (r < nr && lane < n) v[u] = fin[(row0 + r) * n + lane];
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int r = r0 + u * kWaves;
-            if (r < nr && lane < n) buf[r * ld + lane] = v[u];
-        }
-        for (int i = lane + 64; i < n; i += 64) {
+        for (int i0 = 0; i0 < n; i0 += 64) {
+            const int i = i0 + lane;
+            const int ic = i < n ? i : n - 1;
+            T v[kU];
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const int r = r0 + u * kWaves;
-                if (r < nr) v[u] = fin[(row0 + r) * n + i];
+                v[u] = fin[(row0 + (r < nr ? r : nr - 1)) * n + ic];
             }
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const int r = r0 + u * kWaves;
-                if (r < nr) buf[r * ld + i] = v[u];
+                if (r < nr && i < n) buf[r * ld + i] = v[u];
             }
         }
     }
