@@ -48,10 +48,20 @@ def projection_matrices(degree, alpha):
 
 
 def split_shift(sigma):
-    """n = floor(sigma) (a Python int) and alpha = sigma - n, both from FP64."""
+    """n = floor(sigma) (a Python int) and alpha = sigma - n, both from FP64.
+
+    A shift a rounding step below an integer can give alpha = 1 exactly; it
+    is then taken as (n + 1, 0), the same point of the line (A(1) = I = B(0)
+    shifted by one cell), so that one-sided shift derivatives are always
+    taken from the right.
+    """
     sigma = float(sigma)
     n = np.floor(sigma)
-    return int(n), sigma - n
+    alpha = sigma - n
+    if alpha >= 1.0:
+        n += 1.0
+        alpha = 0.0
+    return int(n), alpha
 
 
 def shift_lines(lines, sigma, degree):
