@@ -197,6 +197,88 @@ VP4D_API vp_status vp_strang_step(vp_state* st, void* f, void* f_tmp, int nsteps
                          double tau, double* W_trace, double* moments,
                          void* stream);
 
+/* ------------------------------------------------------------------------
+ * Reverse mode.  Transposes are taken with respect to the Euclidean inner
+ * product of the dof arrays, <a, b> = sum_i a_i b_i (the discrete map is
+ * differentiated as it is computed).
+ * ---------------------------------------------------------------------- */
+
+/*
+ * sldg_advect_adjoint -- transpose of sldg_advect for fixed shifts:
+ * lam_in_c = B(alpha)^T lam_out_{c+n} + A(alpha)^T lam_out_{c+n+1} (cells
+ * mod n_c, n = floor(sigma)).  Arguments as for sldg_advect with
+ * (f_in, f_out) replaced by (lam_out, lam_in); they must not overlap.
+ */
+VP4D_API vp_status sldg_advect_adjoint(int axis, int degree, vp_dtype dt,
+                              const int64_t dims[4], const void* lam_out, void* lam_in,
+                              const double* shift, const int64_t shift_stride[4],
+                              void* stream);
+
+/*
+ * sldg_advect_dshift -- derivative of <lam_out, sldg_advect(f_in)> with
+ * respect to the shift of every line:
+ * g_line[line] = sum_i lam_i . (A'(alpha) u_{i-n-1} + B'(alpha) u_{i-n}),
+ * A' = dA/dalpha, B' = dB/dalpha from the defining integrals (Leibniz rule).
+ *   g_line  device, double, one value per line: prod(dims)/dims[axis]
+ *           entries in C order of the remaining axes.
+ */
+VP4D_API vp_status sldg_advect_dshift(int axis, int degree, vp_dtype dt,
+                             const int64_t dims[4], const void* f_in, const void* lam_out,
+                             const double* shift, const int64_t shift_stride[4],
+                             double* g_line, void* stream);
+
+/* spline_advect_adjoint -- transpose of spline_advect for fixed shifts,
+ * C^{-1} E(alpha)^T lam_out (C is symmetric).  As sldg_advect_adjoint. */
+VP4D_API vp_status spline_advect_adjoint(int axis, vp_dtype dt, const int64_t dims[4],
+                                const void* lam_out, void* lam_in, const double* shift,
+                                const int64_t shift_stride[4], void* stream);
+
+/* spline_advect_dshift -- per-line derivative of <lam_out, spline_advect(f_in)>
+ * with respect to the shift (derivative of the B-spline weights). */
+VP4D_API vp_status spline_advect_dshift(int axis, vp_dtype dt, const int64_t dims[4],
+                               const void* f_in, const void* lam_out, const double* shift,
+                               const int64_t shift_stride[4], double* g_line,
+                               void* stream);
+
+/*
+ * vp_density_adjoint -- transpose of vp_density:
+ * lam[x1][x2][c][e] (+)= rho_bar[x1][x2] * W3_c * W4_e, with the quadrature
+ * weights of vp_density.  accumulate != 0 adds to lam, 0 overwrites it.
+ */
+VP4D_API vp_status vp_density_adjoint(int degree, vp_dtype dt, const int64_t dims[4],
+                             const double* rho_bar, double len_v1, double len_v2,
+                             void* lam, int accumulate, void* stream);
+
+/*
+ * vp_poisson_adjoint -- transpose of the field map of vp_poisson:
+ * rho_bar = P_1^T G1 + P_2^T G2 where (E1, E2) = (P_1 rho, P_2 rho).  On the
+ * uniform grid P_d^T = -P_d (an odd real Fourier multiplier); the SLDG cell
+ * maps are transposed.  Workspace as vp_poisson.
+ */
+VP4D_API vp_status vp_poisson_adjoint(int degree, int64_t n1, int64_t n2, double L1, double L2,
+                             const double* G1, const double* G2, double* rho_bar,
+                             void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * vp_energy_gradient -- W = 1/2 sum w_a w_b (E1^2 + E2^2) of the state f
+ * (written to W when not NULL, device) and lam = dW/df (written).
+ */
+VP4D_API vp_status vp_energy_gradient(vp_state* st, const void* f, void* lam, double* W,
+                             void* stream);
+
+/*
+ * vp_strang_adjoint -- one Strang step backwards.  On entry lam holds
+ * dJ/df^{m+1}; on return it holds dJ/df^m, for the step of size tau taken
+ * from f = f^m (Sec. 2).  The step's internal states are recomputed from f;
+ * the shift dependence of the acceleration sweeps on E(rho(f)) is carried
+ * through the Poisson and density transposes.
+ *   work  device, at least vp_strang_adjoint_workspace(st) bytes (three
+ *         copies of f plus one double per velocity line).
+ */
+VP4D_API size_t vp_strang_adjoint_workspace(const vp_state* st);
+VP4D_API vp_status vp_strang_adjoint(vp_state* st, const void* f, void* lam, double tau,
+                            void* work, size_t ws_bytes, void* stream);
+
 /*
  * Kernel timers of a vp_state.  When enabled, vp_strang_step records HIP
  * events around its launches on `stream`.  vp_timing_read synchronises the

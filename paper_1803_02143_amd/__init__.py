@@ -119,6 +119,85 @@ def spline_advect(axis, f_in, f_out, shift, shift_stride=None, stream=None):
         _f64(shift, "shift"), _lib.i64x4(shift_stride), _stream(stream)))
 
 
+def _lines_numel(f, axis):
+    return f.numel() // f.shape[axis]
+
+
+def sldg_advect_adjoint(axis, degree, lam_out, lam_in, shift, shift_stride=None, stream=None):
+    """Transpose of the SLDG sweep for fixed shifts (C ABI ``sldg_advect_adjoint``)."""
+    if shift_stride is None:
+        shift_stride = broadcast_strides(shift, axis)
+    if lam_out.dtype != lam_in.dtype or lam_out.shape != lam_in.shape:
+        raise ValueError("lam_out and lam_in must match in shape and dtype")
+    _check_shift(shift, lam_out.shape, axis, shift_stride)
+    _check("sldg_advect_adjoint", lib().sldg_advect_adjoint(
+        int(axis), int(degree), _dtype(lam_out), _dims(lam_out), _dev(lam_out, "lam_out"),
+        _dev(lam_in, "lam_in"), _f64(shift, "shift"), _lib.i64x4(shift_stride),
+        _stream(stream)))
+
+
+def sldg_advect_dshift(axis, degree, f_in, lam_out, shift, g_line, shift_stride=None,
+                       stream=None):
+    """Per-line d<lam_out, sweep(f_in)>/d shift (C ABI ``sldg_advect_dshift``)."""
+    if shift_stride is None:
+        shift_stride = broadcast_strides(shift, axis)
+    if f_in.dtype != lam_out.dtype or f_in.shape != lam_out.shape:
+        raise ValueError("f_in and lam_out must match in shape and dtype")
+    _check_shift(shift, f_in.shape, axis, shift_stride)
+    _check("sldg_advect_dshift", lib().sldg_advect_dshift(
+        int(axis), int(degree), _dtype(f_in), _dims(f_in), _dev(f_in, "f_in"),
+        _dev(lam_out, "lam_out"), _f64(shift, "shift"), _lib.i64x4(shift_stride),
+        _f64(g_line, "g_line", _lines_numel(f_in, axis)), _stream(stream)))
+
+
+def spline_advect_adjoint(axis, lam_out, lam_in, shift, shift_stride=None, stream=None):
+    """Transpose of the spline sweep for fixed shifts (C ABI ``spline_advect_adjoint``)."""
+    if shift_stride is None:
+        shift_stride = broadcast_strides(shift, axis)
+    if lam_out.dtype != lam_in.dtype or lam_out.shape != lam_in.shape:
+        raise ValueError("lam_out and lam_in must match in shape and dtype")
+    _check_shift(shift, lam_out.shape, axis, shift_stride)
+    _check("spline_advect_adjoint", lib().spline_advect_adjoint(
+        int(axis), _dtype(lam_out), _dims(lam_out), _dev(lam_out, "lam_out"),
+        _dev(lam_in, "lam_in"), _f64(shift, "shift"), _lib.i64x4(shift_stride),
+        _stream(stream)))
+
+
+def spline_advect_dshift(axis, f_in, lam_out, shift, g_line, shift_stride=None, stream=None):
+    """Per-line d<lam_out, spline sweep(f_in)>/d shift (C ABI ``spline_advect_dshift``)."""
+    if shift_stride is None:
+        shift_stride = broadcast_strides(shift, axis)
+    if f_in.dtype != lam_out.dtype or f_in.shape != lam_out.shape:
+        raise ValueError("f_in and lam_out must match in shape and dtype")
+    _check_shift(shift, f_in.shape, axis, shift_stride)
+    _check("spline_advect_dshift", lib().spline_advect_dshift(
+        int(axis), _dtype(f_in), _dims(f_in), _dev(f_in, "f_in"), _dev(lam_out, "lam_out"),
+        _f64(shift, "shift"), _lib.i64x4(shift_stride),
+        _f64(g_line, "g_line", _lines_numel(f_in, axis)), _stream(stream)))
+
+
+def vp_density_adjoint(degree, rho_bar, len_v1, len_v2, lam, accumulate=False, stream=None):
+    """lam (+)= rho_bar W3 W4 (C ABI ``vp_density_adjoint``)."""
+    if rho_bar.numel() < lam.shape[0] * lam.shape[1]:
+        raise ValueError("rho_bar too small")
+    _check("vp_density_adjoint", lib().vp_density_adjoint(
+        int(degree), _dtype(lam), _dims(lam), _f64(rho_bar, "rho_bar"), float(len_v1),
+        float(len_v2), _dev(lam, "lam"), 1 if accumulate else 0, _stream(stream)))
+
+
+def vp_poisson_adjoint(degree, L1, L2, G1, G2, rho_bar, workspace=None, stream=None):
+    """rho_bar = P_1^T G1 + P_2^T G2 (C ABI ``vp_poisson_adjoint``)."""
+    n1, n2 = G1.shape
+    ws_bytes = vp_poisson_workspace(degree, n1, n2)
+    if workspace is None:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=G1.device)
+    _check("vp_poisson_adjoint", lib().vp_poisson_adjoint(
+        int(degree), int(n1), int(n2), float(L1), float(L2), _f64(G1, "G1", n1 * n2),
+        _f64(G2, "G2", n1 * n2), _f64(rho_bar, "rho_bar", n1 * n2),
+        _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(),
+        _stream(stream)))
+
+
 def vp_density(degree, f, len_v1, len_v2, rho, stream=None):
     """rho[x1][x2] = int f dv (C ABI ``vp_density``); degree -1 = spline grid."""
     _check("vp_density", lib().vp_density(
@@ -198,6 +277,32 @@ class VPState:
             None if W_trace is None else _f64(W_trace, "W_trace", nsteps + 1),
             None if moments is None else _f64(moments, "moments", 4 * (nsteps + 1)),
             _stream(stream)))
+
+    def _check_f(self, t, name):
+        if tuple(t.shape) != self.dims or t.dtype != self.dtype:
+            raise ValueError(f"{name} must be {self.dtype} of shape {self.dims}")
+
+    def adjoint_workspace_bytes(self):
+        return int(lib().vp_strang_adjoint_workspace(self._h))
+
+    def adjoint_workspace(self, device="cuda"):
+        return torch.empty(self.adjoint_workspace_bytes(), dtype=torch.uint8, device=device)
+
+    def adjoint_step(self, f, lam, tau, work, stream=None):
+        """lam: dJ/df^{m+1} in, dJ/df^m out, for the step from f = f^m."""
+        self._check_f(f, "f")
+        self._check_f(lam, "lam")
+        _check("vp_strang_adjoint", lib().vp_strang_adjoint(
+            self._h, _dev(f, "f"), _dev(lam, "lam"), float(tau), _dev(work, "work"),
+            work.numel() * work.element_size(), _stream(stream)))
+
+    def energy_gradient(self, f, lam, W=None, stream=None):
+        """lam = dW/df (and W) for W = 1/2 int |E(f)|^2."""
+        self._check_f(f, "f")
+        self._check_f(lam, "lam")
+        _check("vp_energy_gradient", lib().vp_energy_gradient(
+            self._h, _dev(f, "f"), _dev(lam, "lam"),
+            None if W is None else _f64(W, "W", 1), _stream(stream)))
 
     def timing_enable(self, on=True):
         _check("vp_timing_enable", lib().vp_timing_enable(self._h, 1 if on else 0))

@@ -53,6 +53,24 @@ SIGNATURES = {
     "vp_destroy": (None, [_vp]),
     "vp_strang_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double,
                                       _dp, _dp, _vp]),
+    "sldg_advect_adjoint": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64x4,
+                                           _vp, _vp, _dp, _i64x4, _vp]),
+    "sldg_advect_dshift": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64x4,
+                                          _vp, _vp, _dp, _i64x4, _dp, _vp]),
+    "spline_advect_adjoint": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64x4, _vp, _vp,
+                                             _dp, _i64x4, _vp]),
+    "spline_advect_dshift": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64x4, _vp, _vp,
+                                            _dp, _i64x4, _dp, _vp]),
+    "vp_density_adjoint": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64x4, _dp,
+                                          ctypes.c_double, ctypes.c_double, _vp, ctypes.c_int,
+                                          _vp]),
+    "vp_poisson_adjoint": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                                          ctypes.c_double, ctypes.c_double, _dp, _dp, _dp,
+                                          _vp, ctypes.c_size_t, _vp]),
+    "vp_energy_gradient": (ctypes.c_int, [_vp, _vp, _vp, _dp, _vp]),
+    "vp_strang_adjoint_workspace": (ctypes.c_size_t, [_vp]),
+    "vp_strang_adjoint": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, ctypes.c_size_t,
+                                         _vp]),
     "vp_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "vp_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int64)]),

@@ -21,13 +21,21 @@ AxisGrid axis_grid(int degree, int64_t n, double lo, double len);
 vp_status check_grid_args(int degree, vp_dtype dt, const int64_t dims[4],
                           int64_t* total);
 
+// Sweep (adjoint = false) or its transpose for fixed shifts (adjoint = true).
 vp_status sldg_advect_impl(int axis, int degree, vp_dtype dt,
                            const int64_t dims[4], const void* f_in, void* f_out,
                            const double* shift, const int64_t shift_stride[4],
-                           hipStream_t st);
+                           hipStream_t st, bool adjoint);
 vp_status spline_advect_impl(int axis, vp_dtype dt, const int64_t dims[4],
                              const void* f_in, void* f_out, const double* shift,
-                             const int64_t shift_stride[4], hipStream_t st);
+                             const int64_t shift_stride[4], hipStream_t st, bool adjoint);
+// g_line[line] = d <lam, sweep(f_in)> / d sigma_line (lines in outer-inner order)
+vp_status sldg_dshift_impl(int axis, int degree, vp_dtype dt, const int64_t dims[4],
+                           const void* f_in, const void* lam, const double* shift,
+                           const int64_t shift_stride[4], double* g_line, hipStream_t st);
+vp_status spline_dshift_impl(int axis, vp_dtype dt, const int64_t dims[4], const void* f_in,
+                             const void* lam, const double* shift,
+                             const int64_t shift_stride[4], double* g_line, hipStream_t st);
 vp_status density_impl(int degree, vp_dtype dt, const int64_t dims[4],
                        const void* f, double len_v1, double len_v2, double* rho,
                        hipStream_t st);
@@ -49,5 +57,17 @@ vp_status poisson_impl_shift(int degree, int64_t n1, int64_t n2, double L1, doub
                              const double* rho, double* E1, double* E2, double* W_el,
                              void* workspace, double* sig1, double* sig2, double s1,
                              double s2, hipStream_t st);
+// rho_bar = P_1^T G_1 + P_2^T G_2 (G weighted by the x quadrature when
+// `weighted`); same workspace as poisson_impl.
+vp_status poisson_adjoint_impl(int degree, int64_t n1, int64_t n2, double L1, double L2,
+                               const double* g1, const double* g2, double* rho_bar,
+                               void* workspace, bool weighted, hipStream_t st);
+// lam (+)= rho_bar[x1][x2] W3[v1] W4[v2]
+vp_status density_adjoint_impl(int degree, vp_dtype dt, const int64_t dims[4],
+                               const double* rho_bar, double len_v1, double len_v2,
+                               void* lam, bool accumulate, hipStream_t st);
+// out[b] = scale * sum_{k<K} g[b*K + k]
+vp_status line_sum_impl(const double* g, int64_t nb, int K, double scale, double* out,
+                        hipStream_t st);
 
 }  // namespace vp

@@ -244,6 +244,156 @@ energy_sum(const double* __restrict__ wpart, int nb, double* __restrict__ W) {
     if (threadIdx.x == 0) W[0] = 0.5 * tot;
 }
 
+// ---------------------------------------------------------------- adjoint ---
+// rho_bar = P_1^T G_1 + P_2^T G_2.  On the uniform grid each P_d is the real
+// Fourier multiplier -i k_d/|k|^2, whose transpose has multiplier
+// +i k_d/|k|^2; the SLDG cell maps enter transposed: G is mapped by Q^{-T}
+// before the transforms and the result by Q^T after them.  With `wgrid` set,
+// G_d is first multiplied by the quadrature weights of the x grid (the
+// gradient of W = 1/2 sum w |E|^2 with respect to E is w E).
+
+__global__ void __launch_bounds__(kPB)
+adj_rows_fwd(const double* __restrict__ g1, const double* __restrict__ g2,
+             Cplx* __restrict__ c1, Cplx* __restrict__ c2, int n1, int n2,
+             Transfer tinv, int use_q, int weighted, AxisGrid gx1, AxisGrid gx2) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    Cplx* tw = reinterpret_cast<Cplx*>(smem);         // n2
+    double* y1 = reinterpret_cast<double*>(tw + n2);  // n2
+    double* y2 = y1 + n2;                              // n2
+    const int a = blockIdx.x;
+    twiddles(tw, n2);
+    const int m = use_q ? tinv.m : 1;
+    const int pa = a % m, a0 = a - pa;
+    for (int b = threadIdx.x; b < n2; b += kPB) {
+        const int pb = b % m, b0 = b - pb;
+        double v1 = 0.0, v2 = 0.0;
+        for (int p = 0; p < m; ++p) {
+            double r1 = 0.0, r2 = 0.0;
+            for (int q = 0; q < m; ++q) {
+                const int64_t src = static_cast<int64_t>(a0 + p) * n2 + b0 + q;
+                double x1 = g1[src], x2 = g2[src];
+                if (weighted) {
+                    const double w = gx1.w[(a0 + p) % gx1.m] * gx1.h * gx2.w[(b0 + q) % gx2.m] * gx2.h;
+                    x1 *= w;
+                    x2 *= w;
+                }
+                const double qq = use_q ? tinv.q[q][pb] : 1.0;
+                r1 = fma(qq, x1, r1);
+                r2 = fma(qq, x2, r2);
+            }
+            const double qp = use_q ? tinv.q[p][pa] : 1.0;
+            v1 = fma(qp, r1, v1);
+            v2 = fma(qp, r2, v2);
+        }
+        y1[b] = v1;
+        y2[b] = v2;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < n2; k += kPB) {
+        double re1 = 0.0, im1 = 0.0, re2 = 0.0, im2 = 0.0;
+        int idx = 0;
+        for (int b = 0; b < n2; ++b) {
+            const Cplx w = tw[idx];
+            re1 = fma(y1[b], w.re, re1);
+            im1 = fma(y1[b], w.im, im1);
+            re2 = fma(y2[b], w.re, re2);
+            im2 = fma(y2[b], w.im, im2);
+            idx += k;
+            if (idx >= n2) idx -= n2;
+        }
+        c1[static_cast<int64_t>(a) * n2 + k] = Cplx{re1, im1};
+        c2[static_cast<int64_t>(a) * n2 + k] = Cplx{re2, im2};
+    }
+}
+
+__global__ void __launch_bounds__(kPB)
+adj_cols(const Cplx* __restrict__ c1, const Cplx* __restrict__ c2, Cplx* __restrict__ h,
+         int n1, int n2, double L1, double L2) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    Cplx* tw = reinterpret_cast<Cplx*>(smem);  // n1
+    Cplx* x1 = tw + n1;                        // n1
+    Cplx* x2 = x1 + n1;                        // n1
+    Cplx* rh = x2 + n1;                        // n1
+    const int k2 = blockIdx.x;
+    twiddles(tw, n1);
+    for (int a = threadIdx.x; a < n1; a += kPB) {
+        x1[a] = c1[static_cast<int64_t>(a) * n2 + k2];
+        x2[a] = c2[static_cast<int64_t>(a) * n2 + k2];
+    }
+    __syncthreads();
+    const int m2 = 2 * k2 <= n2 ? k2 : k2 - n2;
+    const bool nyq2 = (n2 % 2 == 0) && 2 * k2 == n2;
+    const double ky = 2.0 * M_PI * m2 / L2;
+    for (int k1 = threadIdx.x; k1 < n1; k1 += kPB) {
+        double r1 = 0.0, i1 = 0.0, r2 = 0.0, i2 = 0.0;
+        int idx = 0;
+        for (int a = 0; a < n1; ++a) {
+            const Cplx w = tw[idx];
+            r1 = fma(x1[a].re, w.re, fma(-x1[a].im, w.im, r1));
+            i1 = fma(x1[a].re, w.im, fma(x1[a].im, w.re, i1));
+            r2 = fma(x2[a].re, w.re, fma(-x2[a].im, w.im, r2));
+            i2 = fma(x2[a].re, w.im, fma(x2[a].im, w.re, i2));
+            idx += k1;
+            if (idx >= n1) idx -= n1;
+        }
+        const int m1 = 2 * k1 <= n1 ? k1 : k1 - n1;
+        const bool nyq = nyq2 || ((n1 % 2 == 0) && 2 * k1 == n1);
+        const double kx = 2.0 * M_PI * m1 / L1;
+        const double kk = kx * kx + ky * ky;
+        if (nyq || kk == 0.0) {
+            rh[k1] = Cplx{0.0, 0.0};
+        } else {
+            // i (kx Y1 + ky Y2) / |k|^2
+            const double sr = (kx * r1 + ky * r2) / kk, si = (kx * i1 + ky * i2) / kk;
+            rh[k1] = Cplx{-si, sr};
+        }
+    }
+    __syncthreads();
+    for (int a = threadIdx.x; a < n1; a += kPB) {
+        double re = 0.0, im = 0.0;
+        int idx = 0;
+        for (int k1 = 0; k1 < n1; ++k1) {
+            const Cplx w = tw[idx];       // conj(w) for the inverse transform
+            const Cplx x = rh[k1];
+            re = fma(x.re, w.re, fma(x.im, w.im, re));
+            im = fma(x.im, w.re, fma(-x.re, w.im, im));
+            idx += a;
+            if (idx >= n1) idx -= n1;
+        }
+        h[static_cast<int64_t>(a) * n2 + k2] = Cplx{re, im};
+    }
+}
+
+__global__ void __launch_bounds__(kPB)
+adj_rows_inv(const Cplx* __restrict__ h, double* __restrict__ rho_bar, int n1, int n2,
+             Transfer t, int use_q) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int m = use_q ? t.m : 1;
+    Cplx* tw = reinterpret_cast<Cplx*>(smem);   // n2
+    Cplx* gl = tw + n2;                         // m * n2
+    double* r = reinterpret_cast<double*>(gl + m * n2);   // m * n2
+    const int a0 = blockIdx.x * m;
+    twiddles(tw, n2);
+    inverse_rows(h, a0, m, n1, n2, tw, gl, r);
+    for (int e = threadIdx.x; e < m * n2; e += kPB) {
+        const int p = e / n2;
+        const int b = e - p * n2;
+        double v;
+        if (use_q) {
+            const int pb = b % m, b0 = b - pb;
+            v = 0.0;
+            for (int pp = 0; pp < m; ++pp) {
+                double acc = 0.0;
+                for (int q = 0; q < m; ++q) acc = fma(t.q[q][pb], r[pp * n2 + b0 + q], acc);
+                v = fma(t.q[pp][p], acc, v);
+            }
+        } else {
+            v = r[e];
+        }
+        rho_bar[static_cast<int64_t>(a0 + p) * n2 + b] = v;
+    }
+}
+
 }  // namespace
 
 static size_t poisson_ws_bytes(int64_t n1, int64_t n2) {
@@ -310,6 +460,44 @@ vp_status poisson_impl(int degree, int64_t n1, int64_t n2, double L1, double L2,
                               nullptr, nullptr, 0.0, 0.0, st);
 }
 
+vp_status poisson_adjoint_impl(int degree, int64_t n1_, int64_t n2_, double L1, double L2,
+                               const double* g1, const double* g2, double* rho_bar,
+                               void* workspace, bool weighted, hipStream_t st) {
+    const int n1 = static_cast<int>(n1_), n2 = static_cast<int>(n2_);
+    const int64_t n = n1_ * n2_;
+    Cplx* c1 = static_cast<Cplx*>(workspace);
+    Cplx* c2 = c1 + n;
+    Cplx* h = c2 + n;
+    Transfer t{}, tinv{};
+    const bool sldg = degree >= 0;
+    int m = 1;
+    if (sldg) {
+        const TransferPair& tp = transfer_pair(degree);
+        m = tp.m;
+        t.m = tinv.m = tp.m;
+        for (int i = 0; i < tp.m; ++i)
+            for (int j = 0; j < tp.m; ++j) {
+                t.q[i][j] = tp.q[i][j];
+                tinv.q[i][j] = tp.qinv[i][j];
+            }
+    }
+    if (rows_inv_lds(m, n2) > 64 * 1024 || static_cast<size_t>(4 * n1) * sizeof(Cplx) > 64 * 1024)
+        return set_error(VP_ERR_UNSUPPORTED, "x grid %d x %d too large for the Poisson kernels",
+                         n1, n2);
+    const AxisGrid gx1 = axis_grid(degree, n1_, 0.0, L1);
+    const AxisGrid gx2 = axis_grid(degree, n2_, 0.0, L2);
+    adj_rows_fwd<<<n1, kPB, n2 * (sizeof(Cplx) + 2 * sizeof(double)), st>>>(
+        g1, g2, c1, c2, n1, n2, tinv, sldg ? 1 : 0, weighted ? 1 : 0, gx1, gx2);
+    vp_status rc = check_launch("adj_rows_fwd");
+    if (rc != VP_OK) return rc;
+    adj_cols<<<n2, kPB, 4 * n1 * sizeof(Cplx), st>>>(c1, c2, h, n1, n2, L1, L2);
+    if ((rc = check_launch("adj_cols")) != VP_OK) return rc;
+    adj_rows_inv<<<n1 / m, kPB, sizeof(Cplx) * (n2 + static_cast<size_t>(m) * n2) +
+                                     sizeof(double) * static_cast<size_t>(m) * n2, st>>>(
+        h, rho_bar, n1, n2, t, sldg ? 1 : 0);
+    return check_launch("adj_rows_inv");
+}
+
 }  // namespace vp
 
 extern "C" size_t vp_poisson_workspace(int degree, int64_t n1, int64_t n2) {
@@ -341,4 +529,29 @@ extern "C" vp_status vp_poisson(int degree, int64_t n1, int64_t n2, double L1,
                          poisson_ws_bytes(n1, n2));
     return poisson_impl(degree, n1, n2, L1, L2, rho, E1, E2, W_el, workspace,
                         static_cast<hipStream_t>(stream));
+}
+
+extern "C" vp_status vp_poisson_adjoint(int degree, int64_t n1, int64_t n2, double L1,
+                                        double L2, const double* G1, const double* G2,
+                                        double* rho_bar, void* workspace, size_t ws_bytes,
+                                        void* stream) {
+    using namespace vp;
+    clear_error();
+    if (degree < -1 || degree > VP_MAX_DEGREE)
+        return set_error(VP_ERR_UNSUPPORTED, "degree %d not in -1..%d", degree, VP_MAX_DEGREE);
+    if (n1 < 1 || n2 < 1 || n1 > 4096 || n2 > 4096)
+        return set_error(VP_ERR_ARG, "grid %lld x %lld out of range", (long long)n1,
+                         (long long)n2);
+    if (degree >= 0 && (n1 % (degree + 1) || n2 % (degree + 1)))
+        return set_error(VP_ERR_ARG, "grid not a multiple of degree+1");
+    if (!(L1 > 0.0) || !(L2 > 0.0)) return set_error(VP_ERR_ARG, "box lengths must be positive");
+    if (!G1 || !G2 || !rho_bar) return set_error(VP_ERR_ARG, "NULL pointer argument");
+    const size_t nb = sizeof(double) * static_cast<size_t>(n1 * n2);
+    if (ranges_overlap(rho_bar, G1, nb) || ranges_overlap(rho_bar, G2, nb))
+        return set_error(VP_ERR_ALIAS, "rho_bar must not overlap G1 or G2");
+    if (!workspace || ws_bytes < poisson_ws_bytes(n1, n2))
+        return set_error(VP_ERR_WORKSPACE, "workspace of %zu bytes needed",
+                         poisson_ws_bytes(n1, n2));
+    return poisson_adjoint_impl(degree, n1, n2, L1, L2, G1, G2, rho_bar, workspace, false,
+                                static_cast<hipStream_t>(stream));
 }

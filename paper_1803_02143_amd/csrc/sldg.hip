@@ -20,6 +20,15 @@
 //  * sldg_row  -- the contiguous axis (v2).  A workgroup stages R whole
 //    lines in LDS with contiguous loads, builds the R line operators once,
 //    and every thread produces one output cell from two LDS cells.
+//
+// The transposed sweep (for reverse-mode differentiation) is the same
+// gather with the transposed operators and the opposite offset:
+// u_bar_c = B^T lam_{c+s} + A^T lam_{c+s+1}; both kernels take it as the
+// template flag ADJ (A_eff = B^T on the first cell of the pair, B_eff = A^T on
+// the second).  The shift derivative d <lam, sweep(u)> / d sigma of a line
+// uses dA/dalpha and dB/dalpha from Leibniz' rule on the defining integrals:
+//   A'_jl = (1/w_j)[L_l(1) L_j(alpha) - sum_q alpha w_q L_l'(alpha xi_q + 1 - alpha) L_j(alpha xi_q)]
+//   B'_jl = (1/w_j)[-L_l(0) L_j(alpha) - sum_q (1-alpha) w_q L_l'((1-alpha) xi_q) L_j(alpha + (1-alpha) xi_q)]
 #include "vp4d_internal.hpp"
 
 namespace vp {
@@ -92,6 +101,94 @@ __device__ __forceinline__ void sldg_operator(const NodeBasis& b, double sigma,
     }
 }
 
+template <int M>
+__device__ __forceinline__ void lagrange_deriv_all(const NodeBasis& b, double t,
+                                                   double D[M]) {
+#pragma unroll
+    for (int l = 0; l < M; ++l) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            if (q == l) continue;
+            double p = b.rd[l][q];
+#pragma unroll
+            for (int k = 0; k < M; ++k)
+                if (k != l && k != q) p *= (t - b.xi[k]) * b.rd[l][k];
+            acc += p;
+        }
+        D[l] = acc;
+    }
+}
+
+// dA/dalpha and dB/dalpha of the line (NaN for a rejected shift).
+template <int M, typename T>
+__device__ __forceinline__ void sldg_operator_deriv(const NodeBasis& b, double sigma,
+                                                    int nc, int& s, T dA[M][M],
+                                                    T dB[M][M]) {
+    double alpha;
+    const bool ok = split_shift(sigma, nc, s, alpha);
+    const double beta = 1.0 - alpha;
+    double la[M], l1[M], l0[M];
+    lagrange_all<M>(b, alpha, la);
+    lagrange_all<M>(b, 1.0, l1);
+    lagrange_all<M>(b, 0.0, l0);
+    double a[M][M], c[M][M];
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            a[j][l] = la[j] * l1[l];
+            c[j][l] = -la[j] * l0[l];
+        }
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        double lo[M], di[M], ro[M], dr[M];
+        const double ta = alpha * b.xi[q];
+        lagrange_all<M>(b, ta, lo);
+        lagrange_deriv_all<M>(b, ta + beta, di);
+        lagrange_all<M>(b, alpha + beta * b.xi[q], ro);
+        lagrange_deriv_all<M>(b, beta * b.xi[q], dr);
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const double wl = alpha * b.w[q] * lo[j];
+            const double wr = beta * b.w[q] * ro[j];
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                a[j][l] = fma(-wl, di[l], a[j][l]);
+                c[j][l] = fma(-wr, dr[l], c[j][l]);
+            }
+        }
+    }
+    const double nan = __builtin_nan("");
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            dA[j][l] = T(ok ? a[j][l] * b.inv_w[j] : nan);
+            dB[j][l] = T(ok ? c[j][l] * b.inv_w[j] : nan);
+        }
+}
+
+// (A, B) -> (B^T, A^T): the pair operators of the transposed sweep.
+template <int M, typename T>
+__device__ __forceinline__ void transpose_pair(T A[M][M], T B[M][M]) {
+    T At[M][M], Bt[M][M];
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            At[j][l] = A[l][j];
+            Bt[j][l] = B[l][j];
+        }
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            A[j][l] = Bt[j][l];
+            B[j][l] = At[j][l];
+        }
+}
+
 // One output cell: out_j = sum_l A_jl left_l + B_jl right_l, stored at
 // out[j * stride].
 template <int M, typename T>
@@ -109,7 +206,7 @@ __device__ __forceinline__ void sldg_cell(const T A[M][M], const T B[M][M],
     }
 }
 
-template <int M, typename T, int AXIS>
+template <int M, typename T, int AXIS, bool ADJ>
 __global__ void __launch_bounds__(kBlock)
 sldg_col(const T* __restrict__ fin, T* __restrict__ fout,
          const double* __restrict__ shift, ShiftMap sm, int64_t outer, int nc,
@@ -122,6 +219,7 @@ sldg_col(const T* __restrict__ fin, T* __restrict__ fout,
     int s;
     T A[M][M], B[M][M];
     sldg_operator<M, T>(basis, shift[shift_offset(sm, o, k)], nc, s, A, B);
+    if (ADJ) transpose_pair<M, T>(A, B);
 
     const int64_t cs = static_cast<int64_t>(M) * inner;  // cell stride
     const T* __restrict__ src = fin + o * nc * cs + k;
@@ -133,7 +231,8 @@ sldg_col(const T* __restrict__ fin, T* __restrict__ fout,
         last[l] = src[(nc - 1) * cs + l * inner];
         prev[l] = last[l];
     }
-    int i = s;  // output cell fed by input cells (c-1, c)
+    // output cell fed by input cells (c-1, c): c+s, or c-1-s for the transpose
+    int i = ADJ ? nc - 1 - s : s;
     // chunks of CU cells: all their loads are issued before the first use
     constexpr int CU = M <= 3 ? 4 : 2;
     int c = 0;
@@ -167,7 +266,7 @@ sldg_col(const T* __restrict__ fin, T* __restrict__ fout,
     }
 }
 
-template <int M, typename T>
+template <int M, typename T, bool ADJ>
 __global__ void __launch_bounds__(kBlock)
 sldg_row(const T* __restrict__ fin, T* __restrict__ fout,
          const double* __restrict__ shift, ShiftMap sm, int64_t nrows, int nc,
@@ -186,6 +285,7 @@ sldg_row(const T* __restrict__ fin, T* __restrict__ fout,
         T A[M][M], B[M][M];
         sldg_operator<M, T>(basis, shift[shift_offset(sm, row0 + r, 0)], nc, s,
                             A, B);
+        if (ADJ) transpose_pair<M, T>(A, B);
         T* op = ops + r * 2 * M * M;
 #pragma unroll
         for (int j = 0; j < M; ++j)
@@ -217,10 +317,12 @@ sldg_row(const T* __restrict__ fin, T* __restrict__ fout,
         const int r = q / nc;
         const int i = q - r * nc;
         const int s = sh[r];
-        int left = i - s - 1;
+        // forward: cells (i-s-1, i-s); transpose: cells (i+s, i+s+1)
+        int left = ADJ ? i + s : i - s - 1;
         if (left < 0) left += nc;
-        int right = i - s;
-        if (right < 0) right += nc;
+        if (left >= nc) left -= nc;
+        int right = left + 1;
+        if (right >= nc) right -= nc;
         const T* op = ops + r * 2 * M * M;
         const T* ul = tile + r * N + left * M;
         const T* ur = tile + r * N + right * M;
@@ -242,7 +344,7 @@ sldg_row(const T* __restrict__ fin, T* __restrict__ fout,
     }
 }
 
-template <int M, typename T>
+template <int M, typename T, bool ADJ>
 vp_status launch_sldg(int axis, const int64_t dims[4], const void* fin,
                       void* fout, const double* shift, const ShiftMap& sm,
                       hipStream_t st) {
@@ -257,13 +359,13 @@ vp_status launch_sldg(int axis, const int64_t dims[4], const void* fin,
         const unsigned grid = blocks_for(outer * inner, kBlock);
         switch (axis) {
             case 0:
-                sldg_col<M, T, 0><<<grid, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, b);
+                sldg_col<M, T, 0, ADJ><<<grid, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, b);
                 break;
             case 1:
-                sldg_col<M, T, 1><<<grid, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, b);
+                sldg_col<M, T, 1, ADJ><<<grid, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, b);
                 break;
             default:
-                sldg_col<M, T, 2><<<grid, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, b);
+                sldg_col<M, T, 2, ADJ><<<grid, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, b);
                 break;
         }
         return check_launch("sldg_col");
@@ -281,21 +383,145 @@ vp_status launch_sldg(int axis, const int64_t dims[4], const void* fin,
         return set_error(VP_ERR_UNSUPPORTED,
                          "sldg_advect: line of %d dofs too long for the LDS tile", N);
     const unsigned grid = blocks_for(outer, R);
-    sldg_row<M, T><<<grid, kBlock, lds, st>>>(in, out, shift, sm, outer, nc, R, b);
+    sldg_row<M, T, ADJ><<<grid, kBlock, lds, st>>>(in, out, shift, sm, outer, nc, R, b);
     return check_launch("sldg_row");
 }
 
-template <typename T>
+template <typename T, bool ADJ>
 vp_status dispatch_degree(int degree, int axis, const int64_t dims[4],
                           const void* fin, void* fout, const double* shift,
                           const ShiftMap& sm, hipStream_t st) {
     switch (degree) {
-        case 0: return launch_sldg<1, T>(axis, dims, fin, fout, shift, sm, st);
-        case 1: return launch_sldg<2, T>(axis, dims, fin, fout, shift, sm, st);
-        case 2: return launch_sldg<3, T>(axis, dims, fin, fout, shift, sm, st);
-        case 3: return launch_sldg<4, T>(axis, dims, fin, fout, shift, sm, st);
-        case 4: return launch_sldg<5, T>(axis, dims, fin, fout, shift, sm, st);
-        case 5: return launch_sldg<6, T>(axis, dims, fin, fout, shift, sm, st);
+        case 0: return launch_sldg<1, T, ADJ>(axis, dims, fin, fout, shift, sm, st);
+        case 1: return launch_sldg<2, T, ADJ>(axis, dims, fin, fout, shift, sm, st);
+        case 2: return launch_sldg<3, T, ADJ>(axis, dims, fin, fout, shift, sm, st);
+        case 3: return launch_sldg<4, T, ADJ>(axis, dims, fin, fout, shift, sm, st);
+        case 4: return launch_sldg<5, T, ADJ>(axis, dims, fin, fout, shift, sm, st);
+        case 5: return launch_sldg<6, T, ADJ>(axis, dims, fin, fout, shift, sm, st);
+        default: return set_error(VP_ERR_UNSUPPORTED, "degree %d", degree);
+    }
+}
+
+// ------------------------------------------------------ shift derivative ---
+
+// Strided lines: one thread per line streams u in memory order and the
+// adjoint lam of the output cells it forms (c+s), accumulating
+// sum_j lam_j (A' u_{c-1} + B' u_c)_j in FP64.
+template <int M, typename T, int AXIS>
+__global__ void __launch_bounds__(kBlock)
+sldg_dshift_col(const T* __restrict__ fin, const T* __restrict__ lam,
+                const double* __restrict__ shift, ShiftMap sm, int64_t outer,
+                int nc, int64_t inner, NodeBasis basis, double* __restrict__ g) {
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (gid >= outer * inner) return;
+    const int64_t o = gid / inner;
+    const int64_t k = gid - o * inner;
+    int s;
+    T dA[M][M], dB[M][M];
+    sldg_operator_deriv<M, T>(basis, shift[shift_offset(sm, o, k)], nc, s, dA, dB);
+    const int64_t cs = static_cast<int64_t>(M) * inner;
+    const T* __restrict__ src = fin + o * nc * cs + k;
+    const T* __restrict__ ls = lam + o * nc * cs + k;
+    T prev[M];
+#pragma unroll
+    for (int l = 0; l < M; ++l) prev[l] = src[(nc - 1) * cs + l * inner];
+    double acc = 0.0;
+    int i = s;
+    for (int c = 0; c < nc; ++c) {
+        T cur[M], lv[M];
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            cur[l] = src[c * cs + l * inner];
+            lv[l] = ls[i * cs + l * inner];
+        }
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            T d = T(0);
+#pragma unroll
+            for (int l = 0; l < M; ++l) d = fma(dA[j][l], prev[l], d);
+#pragma unroll
+            for (int l = 0; l < M; ++l) d = fma(dB[j][l], cur[l], d);
+            acc = fma(static_cast<double>(lv[j]), static_cast<double>(d), acc);
+        }
+#pragma unroll
+        for (int l = 0; l < M; ++l) prev[l] = cur[l];
+        if (++i == nc) i = 0;
+    }
+    g[gid] = acc;
+}
+
+// Contiguous lines: one wavefront per line, lanes over output cells,
+// cross-lane reduction.
+template <int M, typename T>
+__global__ void __launch_bounds__(kBlock)
+sldg_dshift_row(const T* __restrict__ fin, const T* __restrict__ lam,
+                const double* __restrict__ shift, ShiftMap sm, int64_t nrows,
+                int nc, NodeBasis basis, double* __restrict__ g) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+    if (row >= nrows) return;
+    int s;
+    T dA[M][M], dB[M][M];
+    sldg_operator_deriv<M, T>(basis, shift[shift_offset(sm, row, 0)], nc, s, dA, dB);
+    const int N = nc * M;
+    const T* __restrict__ u = fin + row * N;
+    const T* __restrict__ lr = lam + row * N;
+    double acc = 0.0;
+    for (int i = lane; i < nc; i += 64) {
+        int left = i - s - 1;
+        if (left < 0) left += nc;
+        int right = left + 1;
+        if (right >= nc) right -= nc;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            T d = T(0);
+#pragma unroll
+            for (int l = 0; l < M; ++l) d = fma(dA[j][l], u[left * M + l], d);
+#pragma unroll
+            for (int l = 0; l < M; ++l) d = fma(dB[j][l], u[right * M + l], d);
+            acc = fma(static_cast<double>(lr[i * M + j]), static_cast<double>(d), acc);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) g[row] = acc;
+}
+
+template <int M, typename T>
+vp_status launch_dshift(int axis, const int64_t dims[4], const void* fin, const void* lam,
+                        const double* shift, const ShiftMap& sm, double* g, hipStream_t st) {
+    const NodeBasis& b = node_basis(M - 1);
+    int64_t outer = 1, inner = 1;
+    for (int d = 0; d < axis; ++d) outer *= dims[d];
+    for (int d = axis + 1; d < 4; ++d) inner *= dims[d];
+    const int nc = static_cast<int>(dims[axis] / M);
+    const T* in = static_cast<const T*>(fin);
+    const T* l = static_cast<const T*>(lam);
+    if (axis < 3) {
+        const unsigned grid = blocks_for(outer * inner, kBlock);
+        switch (axis) {
+            case 0: sldg_dshift_col<M, T, 0><<<grid, kBlock, 0, st>>>(in, l, shift, sm, outer, nc, inner, b, g); break;
+            case 1: sldg_dshift_col<M, T, 1><<<grid, kBlock, 0, st>>>(in, l, shift, sm, outer, nc, inner, b, g); break;
+            default: sldg_dshift_col<M, T, 2><<<grid, kBlock, 0, st>>>(in, l, shift, sm, outer, nc, inner, b, g); break;
+        }
+        return check_launch("sldg_dshift_col");
+    }
+    sldg_dshift_row<M, T><<<blocks_for(outer, kBlock / 64), kBlock, 0, st>>>(in, l, shift, sm,
+                                                                             outer, nc, b, g);
+    return check_launch("sldg_dshift_row");
+}
+
+template <typename T>
+vp_status dispatch_dshift(int degree, int axis, const int64_t dims[4], const void* fin,
+                          const void* lam, const double* shift, const ShiftMap& sm,
+                          double* g, hipStream_t st) {
+    switch (degree) {
+        case 0: return launch_dshift<1, T>(axis, dims, fin, lam, shift, sm, g, st);
+        case 1: return launch_dshift<2, T>(axis, dims, fin, lam, shift, sm, g, st);
+        case 2: return launch_dshift<3, T>(axis, dims, fin, lam, shift, sm, g, st);
+        case 3: return launch_dshift<4, T>(axis, dims, fin, lam, shift, sm, g, st);
+        case 4: return launch_dshift<5, T>(axis, dims, fin, lam, shift, sm, g, st);
+        case 5: return launch_dshift<6, T>(axis, dims, fin, lam, shift, sm, g, st);
         default: return set_error(VP_ERR_UNSUPPORTED, "degree %d", degree);
     }
 }
@@ -305,14 +531,49 @@ vp_status dispatch_degree(int degree, int axis, const int64_t dims[4],
 vp_status sldg_advect_impl(int axis, int degree, vp_dtype dt,
                            const int64_t dims[4], const void* f_in, void* f_out,
                            const double* shift, const int64_t shift_stride[4],
-                           hipStream_t st) {
+                           hipStream_t st, bool adjoint) {
     const ShiftMap sm = make_shift_map(axis, dims, shift_stride);
     if (dt == VP_F64)
-        return dispatch_degree<double>(degree, axis, dims, f_in, f_out, shift, sm, st);
-    return dispatch_degree<float>(degree, axis, dims, f_in, f_out, shift, sm, st);
+        return adjoint
+                   ? dispatch_degree<double, true>(degree, axis, dims, f_in, f_out, shift, sm, st)
+                   : dispatch_degree<double, false>(degree, axis, dims, f_in, f_out, shift, sm, st);
+    return adjoint
+               ? dispatch_degree<float, true>(degree, axis, dims, f_in, f_out, shift, sm, st)
+               : dispatch_degree<float, false>(degree, axis, dims, f_in, f_out, shift, sm, st);
+}
+
+vp_status sldg_dshift_impl(int axis, int degree, vp_dtype dt, const int64_t dims[4],
+                           const void* f_in, const void* lam, const double* shift,
+                           const int64_t shift_stride[4], double* g_line, hipStream_t st) {
+    const ShiftMap sm = make_shift_map(axis, dims, shift_stride);
+    if (dt == VP_F64)
+        return dispatch_dshift<double>(degree, axis, dims, f_in, lam, shift, sm, g_line, st);
+    return dispatch_dshift<float>(degree, axis, dims, f_in, lam, shift, sm, g_line, st);
 }
 
 }  // namespace vp
+
+namespace {
+
+vp_status check_sldg_args(int axis, int degree, vp_dtype dt, const int64_t dims[4],
+                          const void* a, const void* b, const double* shift,
+                          const int64_t shift_stride[4], int64_t* total) {
+    using namespace vp;
+    if (axis < 0 || axis > 3) return set_error(VP_ERR_ARG, "axis %d not in 0..3", axis);
+    if (degree < 0 || degree > VP_MAX_DEGREE)
+        return set_error(VP_ERR_UNSUPPORTED, "degree %d not in 0..%d", degree,
+                         VP_MAX_DEGREE);
+    if (dt != VP_F32 && dt != VP_F64) return set_error(VP_ERR_ARG, "bad dtype %d", (int)dt);
+    vp_status rc = check_dims(dims, total);
+    if (rc != VP_OK) return rc;
+    if (dims[axis] % (degree + 1))
+        return set_error(VP_ERR_ARG, "dims[%d] = %lld is not a multiple of degree+1 = %d",
+                         axis, (long long)dims[axis], degree + 1);
+    if (!a || !b || !shift) return set_error(VP_ERR_ARG, "NULL pointer argument");
+    return check_shift_strides(axis, dims, shift_stride);
+}
+
+}  // namespace
 
 extern "C" vp_status sldg_advect(int axis, int degree, vp_dtype dt,
                                  const int64_t dims[4], const void* f_in,
@@ -320,22 +581,44 @@ extern "C" vp_status sldg_advect(int axis, int degree, vp_dtype dt,
                                  const int64_t shift_stride[4], void* stream) {
     using namespace vp;
     clear_error();
-    if (axis < 0 || axis > 3) return set_error(VP_ERR_ARG, "axis %d not in 0..3", axis);
-    if (degree < 0 || degree > VP_MAX_DEGREE)
-        return set_error(VP_ERR_UNSUPPORTED, "degree %d not in 0..%d", degree,
-                         VP_MAX_DEGREE);
-    if (dt != VP_F32 && dt != VP_F64) return set_error(VP_ERR_ARG, "bad dtype %d", (int)dt);
     int64_t total = 0;
-    vp_status rc = check_dims(dims, &total);
-    if (rc != VP_OK) return rc;
-    if (dims[axis] % (degree + 1))
-        return set_error(VP_ERR_ARG, "dims[%d] = %lld is not a multiple of degree+1 = %d",
-                         axis, (long long)dims[axis], degree + 1);
-    if (!f_in || !f_out || !shift) return set_error(VP_ERR_ARG, "NULL pointer argument");
-    rc = check_shift_strides(axis, dims, shift_stride);
+    vp_status rc = check_sldg_args(axis, degree, dt, dims, f_in, f_out, shift, shift_stride,
+                                   &total);
     if (rc != VP_OK) return rc;
     if (ranges_overlap(f_in, f_out, static_cast<size_t>(total) * dtype_size(dt)))
         return set_error(VP_ERR_ALIAS, "f_in and f_out overlap");
     return sldg_advect_impl(axis, degree, dt, dims, f_in, f_out, shift, shift_stride,
-                            static_cast<hipStream_t>(stream));
+                            static_cast<hipStream_t>(stream), false);
+}
+
+extern "C" vp_status sldg_advect_adjoint(int axis, int degree, vp_dtype dt,
+                                         const int64_t dims[4], const void* lam_out,
+                                         void* lam_in, const double* shift,
+                                         const int64_t shift_stride[4], void* stream) {
+    using namespace vp;
+    clear_error();
+    int64_t total = 0;
+    vp_status rc = check_sldg_args(axis, degree, dt, dims, lam_out, lam_in, shift,
+                                   shift_stride, &total);
+    if (rc != VP_OK) return rc;
+    if (ranges_overlap(lam_out, lam_in, static_cast<size_t>(total) * dtype_size(dt)))
+        return set_error(VP_ERR_ALIAS, "lam_out and lam_in overlap");
+    return sldg_advect_impl(axis, degree, dt, dims, lam_out, lam_in, shift, shift_stride,
+                            static_cast<hipStream_t>(stream), true);
+}
+
+extern "C" vp_status sldg_advect_dshift(int axis, int degree, vp_dtype dt,
+                                        const int64_t dims[4], const void* f_in,
+                                        const void* lam_out, const double* shift,
+                                        const int64_t shift_stride[4], double* g_line,
+                                        void* stream) {
+    using namespace vp;
+    clear_error();
+    int64_t total = 0;
+    vp_status rc = check_sldg_args(axis, degree, dt, dims, f_in, lam_out, shift,
+                                   shift_stride, &total);
+    if (rc != VP_OK) return rc;
+    if (!g_line) return set_error(VP_ERR_ARG, "NULL pointer argument");
+    return sldg_dshift_impl(axis, degree, dt, dims, f_in, lam_out, shift, shift_stride,
+                            g_line, static_cast<hipStream_t>(stream));
 }

@@ -205,15 +205,87 @@ __device__ __forceinline__ int first_tap(int i, int s, int n) {
     return j;
 }
 
+enum { kFwd = 0, kAdj = 1, kDshift = 2 };
+
+// Longest segment a thread owns: tiles hold at most kTileBytes, so a
+// segment has at most kTileBytes / (kBlock * sizeof(T)) points.
+template <typename T>
+struct SegMax {
+    static constexpr int value = 48 * 1024 / (256 * static_cast<int>(sizeof(T)));
+};
+
+// d beta_q / d alpha times -6r (derivative of spline_weights).
+template <typename T>
+__device__ __forceinline__ void spline_dweights(double sigma, int n, int& s, T wq[4]) {
+    double alpha;
+    const bool ok = split_shift(sigma, n, s, alpha);
+    const double t = 1.0 - alpha;
+    const double g = -6.0 * (1.7320508075688772 - 2.0) / 6.0;  // -6r/6
+    // 6 d beta_q / dt; d/d alpha = -d/dt
+    double d0 = -3.0 * (1.0 - t) * (1.0 - t);
+    double d1 = 9.0 * t * t - 12.0 * t;
+    double d2 = -9.0 * t * t + 6.0 * t + 3.0;
+    double d3 = 3.0 * t * t;
+    if (!ok) d0 = d1 = d2 = d3 = __builtin_nan("");
+    wq[0] = T(-g * d0);
+    wq[1] = T(-g * d1);
+    wq[2] = T(-g * d2);
+    wq[3] = T(-g * d3);
+}
+
+// Transposed evaluation on a segment, in place, called by every thread:
+// mu_k = w3 lam_{k+s-1} + w2 lam_{k+s} + w1 lam_{k+s+1} + w0 lam_{k+s+2}
+// for k in [b, e) (the gather form of the four-tap scatter).
+template <typename T>
+__device__ __forceinline__ void transposed_taps(T* p, int stride, int b, int e, int s, int n,
+                                                T w0, T w1, T w2, T w3, bool active) {
+    constexpr int SM = SegMax<T>::value;
+    T mu[SM];
+    if (active) {
+        int j = b + s - 1;
+        if (j < 0) j += n;
+        if (j >= n) j -= n;
+        T c0 = p[j * stride];
+        j = next_idx(j, n);
+        T c1 = p[j * stride];
+        j = next_idx(j, n);
+        T c2 = p[j * stride];
+        j = next_idx(j, n);
+        T c3 = p[j * stride];
+#pragma unroll
+        for (int t = 0; t < SM; ++t) {
+            if (b + t < e) {
+                mu[t] = fma(w0, c3, fma(w1, c2, fma(w2, c1, w3 * c0)));
+                c0 = c1;
+                c1 = c2;
+                c2 = c3;
+                j = next_idx(j, n);
+                c3 = p[j * stride];
+            }
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int t = 0; t < SM; ++t)
+            if (b + t < e) p[(b + t) * stride] = mu[t];
+    }
+    __syncthreads();
+}
+
 // Lines along a strided axis.  Thread t owns line l = t % L (L adjacent
 // lines of the fastest axis) and segment q = t / L of that line, for the
 // load, the solve and the evaluation alike.
-template <typename T, int AXIS>
+//   kFwd:    fout = E(alpha) C^{-1} fin
+//   kAdj:    fout = C^{-1} E(alpha)^T fin            (fin = adjoint of the output)
+//   kDshift: g[line] = <lam, E'(alpha) C^{-1} fin>    (per-line shift derivative)
+template <typename T, int AXIS, int MODE>
 __global__ void __launch_bounds__(kBlock)
-spline_col(const T* __restrict__ fin, T* __restrict__ fout,
-           const double* __restrict__ shift, ShiftMap sm, int64_t inner, int L,
-           int64_t tiles_per_outer, SplineParams<T> sp) {
+spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ lam,
+           double* __restrict__ g, const double* __restrict__ shift, ShiftMap sm,
+           int64_t inner, int L, int64_t tiles_per_outer, SplineParams<T> sp) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[MODE == kDshift ? kBlock : 1];
     const int n = sp.n;
     T* buf = reinterpret_cast<T*>(smem);   // [n][L]
 
@@ -229,7 +301,6 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout,
     const int e = min(n, b + S);
     const bool active = l < nl && b < e;
     const T* __restrict__ src = fin + base + l;
-    T* __restrict__ dst = fout + base + l;
     if (active) {
         // batches of kU independent loads keep many requests in flight
         int i = b;
@@ -246,16 +317,31 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout,
     T w0 = T(0), w1 = T(0), w2 = T(0), w3 = T(0);
     if (active) {
         T wq[4];
-        spline_weights<T>(shift[shift_offset(sm, o, k0 + l)], n, s, wq);
+        const double sigma = shift[shift_offset(sm, o, k0 + l)];
+        if (MODE == kDshift)
+            spline_dweights<T>(sigma, n, s, wq);
+        else
+            spline_weights<T>(sigma, n, s, wq);
         w0 = wq[0];
         w1 = wq[1];
         w2 = wq[2];
         w3 = wq[3];
     }
     __syncthreads();
+    if (MODE == kAdj) transposed_taps<T>(buf + l, L, b, e, s, n, w0, w1, w2, w3, active);
     spline_solve_segment<T>(buf + l, L, b, e, active, sp);
+    if (MODE == kAdj) {
+        if (active) {
+            T* __restrict__ dst = fout + base + l;
+            for (int i = b; i < e; ++i) dst[static_cast<int64_t>(i) * inner] = buf[i * L + l];
+        }
+        return;
+    }
+    double acc = 0.0;
     if (active) {
         // sliding window over omega_{i-s-2 .. i-s+1}
+        T* __restrict__ dst = fout + base + l;
+        const T* __restrict__ lm = lam + base + l;
         int j = first_tap(b, s, n);
         T c0 = buf[j * L + l];
         j = next_idx(j, n);
@@ -265,23 +351,30 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout,
         j = next_idx(j, n);
         T c3 = buf[j * L + l];
         int i = b;
-        for (; i + 4 <= e; i += 4) {
-            const int j4 = next_idx(j, n), j5 = next_idx(j4, n);
-            const int j6 = next_idx(j5, n), j7 = next_idx(j6, n);
-            const T c4 = buf[j4 * L + l], c5 = buf[j5 * L + l];
-            const T c6 = buf[j6 * L + l], c7 = buf[j7 * L + l];
-            dst[static_cast<int64_t>(i) * inner] = fma(w3, c3, fma(w2, c2, fma(w1, c1, w0 * c0)));
-            dst[static_cast<int64_t>(i + 1) * inner] = fma(w3, c4, fma(w2, c3, fma(w1, c2, w0 * c1)));
-            dst[static_cast<int64_t>(i + 2) * inner] = fma(w3, c5, fma(w2, c4, fma(w1, c3, w0 * c2)));
-            dst[static_cast<int64_t>(i + 3) * inner] = fma(w3, c6, fma(w2, c5, fma(w1, c4, w0 * c3)));
-            c0 = c4;
-            c1 = c5;
-            c2 = c6;
-            c3 = c7;
-            j = j7;
+        if (MODE == kFwd) {
+            for (; i + 4 <= e; i += 4) {
+                const int j4 = next_idx(j, n), j5 = next_idx(j4, n);
+                const int j6 = next_idx(j5, n), j7 = next_idx(j6, n);
+                const T c4 = buf[j4 * L + l], c5 = buf[j5 * L + l];
+                const T c6 = buf[j6 * L + l], c7 = buf[j7 * L + l];
+                dst[static_cast<int64_t>(i) * inner] = fma(w3, c3, fma(w2, c2, fma(w1, c1, w0 * c0)));
+                dst[static_cast<int64_t>(i + 1) * inner] = fma(w3, c4, fma(w2, c3, fma(w1, c2, w0 * c1)));
+                dst[static_cast<int64_t>(i + 2) * inner] = fma(w3, c5, fma(w2, c4, fma(w1, c3, w0 * c2)));
+                dst[static_cast<int64_t>(i + 3) * inner] = fma(w3, c6, fma(w2, c5, fma(w1, c4, w0 * c3)));
+                c0 = c4;
+                c1 = c5;
+                c2 = c6;
+                c3 = c7;
+                j = j7;
+            }
         }
         for (; i < e; ++i) {
-            dst[static_cast<int64_t>(i) * inner] = fma(w3, c3, fma(w2, c2, fma(w1, c1, w0 * c0)));
+            const T v = fma(w3, c3, fma(w2, c2, fma(w1, c1, w0 * c0)));
+            if (MODE == kFwd)
+                dst[static_cast<int64_t>(i) * inner] = v;
+            else
+                acc = fma(static_cast<double>(lm[static_cast<int64_t>(i) * inner]),
+                          static_cast<double>(v), acc);
             c0 = c1;
             c1 = c2;
             c2 = c3;
@@ -289,17 +382,26 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout,
             c3 = buf[j * L + l];
         }
     }
+    if (MODE == kDshift) {
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        if (threadIdx.x < nl) {
+            double t = 0.0;
+            for (int q = 0; q < Q; ++q) t += red[q * L + threadIdx.x];
+            g[o * inner + k0 + threadIdx.x] = t;
+        }
+    }
 }
 
 // Lines along the contiguous axis.  Loads and stores go row by row, one
 // wavefront per row (consecutive lanes, consecutive addresses; the row's
 // weights and shift are wavefront-uniform); the solve gives thread t row
-// r = t % R and segment q = t / R.
-template <typename T>
+// r = t % R and segment q = t / R.  Modes as for spline_col.
+template <typename T, int MODE>
 __global__ void __launch_bounds__(kBlock)
-spline_row(const T* __restrict__ fin, T* __restrict__ fout,
-           const double* __restrict__ shift, ShiftMap sm, int64_t nrows, int R,
-           SplineParams<T> sp) {
+spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ lam,
+           double* __restrict__ g, const double* __restrict__ shift, ShiftMap sm,
+           int64_t nrows, int R, SplineParams<T> sp) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = sp.n;
     const int ld = n + 1;
@@ -312,9 +414,9 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout,
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     constexpr int kWaves = kBlock / 64;
-    // rows r = wave, wave + 4, ...; kU loads in flight per lane
-    // clamped indices instead of branches, so that the kU loads of a batch
-    // issue back to back; only the LDS stores are guarded
+    // rows r = wave, wave + 4, ...; clamped indices instead of branches, so
+    // that the kU loads of a batch issue back to back; only the LDS stores
+    // are guarded
     for (int r0 = wave; r0 < nr; r0 += kWaves * kU) {
         for (int i0 = 0; i0 < n; i0 += 64) {
             const int i = i0 + lane;
@@ -336,7 +438,11 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout,
         const int r = threadIdx.x;
         int s;
         T wq[4];
-        spline_weights<T>(shift[shift_offset(sm, row0 + r, 0)], n, s, wq);
+        const double sigma = shift[shift_offset(sm, row0 + r, 0)];
+        if (MODE == kDshift)
+            spline_dweights<T>(sigma, n, s, wq);
+        else
+            spline_weights<T>(sigma, n, s, wq);
         wts[4 * r + 0] = wq[0];
         wts[4 * r + 1] = wq[1];
         wts[4 * r + 2] = wq[2];
@@ -350,18 +456,38 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout,
         const int S = (n + Q - 1) / Q;
         const int b = min(n, (static_cast<int>(threadIdx.x) / R) * S);
         const int e = min(n, b + S);
-        spline_solve_segment<T>(buf + r * ld, 1, b, e, r < nr && b < e, sp);
+        const bool active = r < nr && b < e;
+        if (MODE == kAdj)
+            transposed_taps<T>(buf + r * ld, 1, b, e, active ? sh[r] : 0, n,
+                               active ? wts[4 * r] : T(0), active ? wts[4 * r + 1] : T(0),
+                               active ? wts[4 * r + 2] : T(0), active ? wts[4 * r + 3] : T(0),
+                               active);
+        spline_solve_segment<T>(buf + r * ld, 1, b, e, active, sp);
     }
     for (int r = wave; r < nr; r += kWaves) {
         const T* row = buf + r * ld;
+        T* __restrict__ dst = fout + (row0 + r) * n;
+        if (MODE == kAdj) {
+            for (int i = lane; i < n; i += 64) dst[i] = row[i];
+            continue;
+        }
         const T w0 = wts[4 * r + 0], w1 = wts[4 * r + 1];
         const T w2 = wts[4 * r + 2], w3 = wts[4 * r + 3];
         const int s = sh[r];
-        T* __restrict__ dst = fout + (row0 + r) * n;
+        double acc = 0.0;
         for (int i = lane; i < n; i += 64) {
             const int j0 = first_tap(i, s, n);
             const int j1 = next_idx(j0, n), j2 = next_idx(j1, n), j3 = next_idx(j2, n);
-            dst[i] = fma(w3, row[j3], fma(w2, row[j2], fma(w1, row[j1], w0 * row[j0])));
+            const T v = fma(w3, row[j3], fma(w2, row[j2], fma(w1, row[j1], w0 * row[j0])));
+            if (MODE == kFwd)
+                dst[i] = v;
+            else
+                acc = fma(static_cast<double>(lam[(row0 + r) * n + i]), static_cast<double>(v), acc);
+        }
+        if (MODE == kDshift) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if (lane == 0) g[row0 + r] = acc;
         }
     }
 }
@@ -381,10 +507,10 @@ SplineParams<T> make_params(int n) {
 
 constexpr size_t kTileBytes = 48 * 1024;
 
-template <typename T>
+template <typename T, int MODE>
 vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
-                        void* fout, const double* shift, const ShiftMap& sm,
-                        hipStream_t st) {
+                        void* fout, const void* lam, double* g, const double* shift,
+                        const ShiftMap& sm, hipStream_t st) {
     int64_t outer = 1, inner = 1;
     for (int d = 0; d < axis; ++d) outer *= dims[d];
     for (int d = axis + 1; d < 4; ++d) inner *= dims[d];
@@ -392,6 +518,7 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
     const SplineParams<T> sp = make_params<T>(n);
     const T* in = static_cast<const T*>(fin);
     T* out = static_cast<T*>(fout);
+    const T* lm = static_cast<const T*>(lam);
     if (axis < 3) {
         // lines per tile: a power of two dividing the fastest block when one
         // of at least 16 does, within the LDS budget
@@ -401,7 +528,7 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
         while (L > 1 && (static_cast<size_t>(n) * L * sizeof(T) > kTileBytes || L / 2 >= inner))
             L /= 2;
         const size_t lds = static_cast<size_t>(n) * L * sizeof(T);
-        if (lds > 64 * 1024)
+        if (lds > kTileBytes)
             return set_error(VP_ERR_UNSUPPORTED,
                              "spline_advect: line of %d points too long for the LDS tile", n);
         const int64_t tiles = (inner + L - 1) / L;
@@ -411,21 +538,22 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
         const unsigned grid = static_cast<unsigned>(grid64);
         switch (axis) {
             case 0:
-                spline_col<T, 0><<<grid, kBlock, lds, st>>>(in, out, shift, sm, inner, L, tiles, sp);
+                spline_col<T, 0, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, inner, L, tiles, sp);
                 break;
             case 1:
-                spline_col<T, 1><<<grid, kBlock, lds, st>>>(in, out, shift, sm, inner, L, tiles, sp);
+                spline_col<T, 1, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, inner, L, tiles, sp);
                 break;
             default:
-                spline_col<T, 2><<<grid, kBlock, lds, st>>>(in, out, shift, sm, inner, L, tiles, sp);
+                spline_col<T, 2, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, inner, L, tiles, sp);
                 break;
         }
         return check_launch("spline_col");
     }
-    int R = static_cast<int>(kTileBytes / ((static_cast<size_t>(n) + 1) * sizeof(T)));
-    if (R > 64) R = 64;
-    if (R > 4) R &= ~3;   // whole rows per wavefront in the load and store loops
-    if (R < 1)
+    // rows per tile: a power of two (so every segment fits SegMax) within
+    // the LDS budget
+    int R = 64;
+    while (R > 1 && static_cast<size_t>(R) * (n + 1) * sizeof(T) > kTileBytes) R /= 2;
+    if (static_cast<size_t>(R) * (n + 1) * sizeof(T) > kTileBytes)
         return set_error(VP_ERR_UNSUPPORTED,
                          "spline_advect: line of %d points too long for the LDS tile", n);
     const size_t lds = static_cast<size_t>(R) * (n + 1) * sizeof(T) +
@@ -433,7 +561,8 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
     const int64_t grid64 = (outer + R - 1) / R;
     if (grid64 >= (int64_t(1) << 31))
         return set_error(VP_ERR_UNSUPPORTED, "spline_advect: grid too large");
-    spline_row<T><<<static_cast<unsigned>(grid64), kBlock, lds, st>>>(in, out, shift, sm, outer, R, sp);
+    spline_row<T, MODE><<<static_cast<unsigned>(grid64), kBlock, lds, st>>>(in, out, lm, g, shift,
+                                                                          sm, outer, R, sp);
     return check_launch("spline_row");
 }
 
@@ -441,13 +570,41 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
 
 vp_status spline_advect_impl(int axis, vp_dtype dt, const int64_t dims[4],
                              const void* f_in, void* f_out, const double* shift,
-                             const int64_t shift_stride[4], hipStream_t st) {
+                             const int64_t shift_stride[4], hipStream_t st, bool adjoint) {
     const ShiftMap sm = make_shift_map(axis, dims, shift_stride);
-    if (dt == VP_F64) return launch_spline<double>(axis, dims, f_in, f_out, shift, sm, st);
-    return launch_spline<float>(axis, dims, f_in, f_out, shift, sm, st);
+    if (dt == VP_F64)
+        return adjoint ? launch_spline<double, kAdj>(axis, dims, f_in, f_out, nullptr, nullptr, shift, sm, st)
+                       : launch_spline<double, kFwd>(axis, dims, f_in, f_out, nullptr, nullptr, shift, sm, st);
+    return adjoint ? launch_spline<float, kAdj>(axis, dims, f_in, f_out, nullptr, nullptr, shift, sm, st)
+                   : launch_spline<float, kFwd>(axis, dims, f_in, f_out, nullptr, nullptr, shift, sm, st);
+}
+
+vp_status spline_dshift_impl(int axis, vp_dtype dt, const int64_t dims[4], const void* f_in,
+                             const void* lam, const double* shift,
+                             const int64_t shift_stride[4], double* g_line, hipStream_t st) {
+    const ShiftMap sm = make_shift_map(axis, dims, shift_stride);
+    if (dt == VP_F64)
+        return launch_spline<double, kDshift>(axis, dims, f_in, nullptr, lam, g_line, shift, sm, st);
+    return launch_spline<float, kDshift>(axis, dims, f_in, nullptr, lam, g_line, shift, sm, st);
 }
 
 }  // namespace vp
+
+namespace {
+
+vp_status check_spline_args(int axis, vp_dtype dt, const int64_t dims[4], const void* a,
+                            const void* b, const double* shift,
+                            const int64_t shift_stride[4], int64_t* total) {
+    using namespace vp;
+    if (axis < 0 || axis > 3) return set_error(VP_ERR_ARG, "axis %d not in 0..3", axis);
+    if (dt != VP_F32 && dt != VP_F64) return set_error(VP_ERR_ARG, "bad dtype %d", (int)dt);
+    vp_status rc = check_dims(dims, total);
+    if (rc != VP_OK) return rc;
+    if (!a || !b || !shift) return set_error(VP_ERR_ARG, "NULL pointer argument");
+    return check_shift_strides(axis, dims, shift_stride);
+}
+
+}  // namespace
 
 extern "C" vp_status spline_advect(int axis, vp_dtype dt, const int64_t dims[4],
                                    const void* f_in, void* f_out,
@@ -455,16 +612,42 @@ extern "C" vp_status spline_advect(int axis, vp_dtype dt, const int64_t dims[4],
                                    const int64_t shift_stride[4], void* stream) {
     using namespace vp;
     clear_error();
-    if (axis < 0 || axis > 3) return set_error(VP_ERR_ARG, "axis %d not in 0..3", axis);
-    if (dt != VP_F32 && dt != VP_F64) return set_error(VP_ERR_ARG, "bad dtype %d", (int)dt);
     int64_t total = 0;
-    vp_status rc = check_dims(dims, &total);
-    if (rc != VP_OK) return rc;
-    if (!f_in || !f_out || !shift) return set_error(VP_ERR_ARG, "NULL pointer argument");
-    rc = check_shift_strides(axis, dims, shift_stride);
+    vp_status rc = check_spline_args(axis, dt, dims, f_in, f_out, shift, shift_stride, &total);
     if (rc != VP_OK) return rc;
     if (ranges_overlap(f_in, f_out, static_cast<size_t>(total) * dtype_size(dt)))
         return set_error(VP_ERR_ALIAS, "f_in and f_out overlap");
     return spline_advect_impl(axis, dt, dims, f_in, f_out, shift, shift_stride,
+                              static_cast<hipStream_t>(stream), false);
+}
+
+extern "C" vp_status spline_advect_adjoint(int axis, vp_dtype dt, const int64_t dims[4],
+                                           const void* lam_out, void* lam_in,
+                                           const double* shift,
+                                           const int64_t shift_stride[4], void* stream) {
+    using namespace vp;
+    clear_error();
+    int64_t total = 0;
+    vp_status rc = check_spline_args(axis, dt, dims, lam_out, lam_in, shift, shift_stride,
+                                     &total);
+    if (rc != VP_OK) return rc;
+    if (ranges_overlap(lam_out, lam_in, static_cast<size_t>(total) * dtype_size(dt)))
+        return set_error(VP_ERR_ALIAS, "lam_out and lam_in overlap");
+    return spline_advect_impl(axis, dt, dims, lam_out, lam_in, shift, shift_stride,
+                              static_cast<hipStream_t>(stream), true);
+}
+
+extern "C" vp_status spline_advect_dshift(int axis, vp_dtype dt, const int64_t dims[4],
+                                          const void* f_in, const void* lam_out,
+                                          const double* shift,
+                                          const int64_t shift_stride[4], double* g_line,
+                                          void* stream) {
+    using namespace vp;
+    clear_error();
+    int64_t total = 0;
+    vp_status rc = check_spline_args(axis, dt, dims, f_in, lam_out, shift, shift_stride, &total);
+    if (rc != VP_OK) return rc;
+    if (!g_line) return set_error(VP_ERR_ARG, "NULL pointer argument");
+    return spline_dshift_impl(axis, dt, dims, f_in, lam_out, shift, shift_stride, g_line,
                               static_cast<hipStream_t>(stream));
 }

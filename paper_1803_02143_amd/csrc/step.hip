@@ -26,6 +26,7 @@ struct vp_state {
     double* buf;  // one device allocation holding every 2D array below
     double *rho, *e1, *e2, *sig_v1, *sig_v2, *sig_x1, *sig_x2, *vnode1, *vnode2;
     double* partial;  // 4 * n1 * n2
+    double *gs1, *gs2, *rho_bar;  // adjoint: shift gradients and transposed density
     void* pws;        // Poisson workspace
     bool timing;
     std::vector<hipEvent_t> ev[VP_TIMER_COUNT];  // start/stop pairs
@@ -62,24 +63,48 @@ void mark(vp_state* st, int timer, hipStream_t s) {
     st->ev[timer].push_back(e);
 }
 
-vp_status sweep(vp_state* st, int axis, const void* in, void* out,
-                const double* shift, hipStream_t s) {
-    int64_t stride[4] = {0, 0, 0, 0};
+// Shift strides of the step: x sweeps one value per v node, v sweeps one
+// value per (x1, x2) point.
+void step_strides(const vp_state* st, int axis, int64_t stride[4]) {
+    stride[0] = stride[1] = stride[2] = stride[3] = 0;
     if (axis == 0) stride[2] = 1;
     else if (axis == 1) stride[3] = 1;
     else {
         stride[0] = st->dims[1];
         stride[1] = 1;
     }
-    mark(st, VP_TIMER_SWEEP_X1 + axis, s);
+}
+
+vp_status sweep(vp_state* st, int axis, const void* in, void* out,
+                const double* shift, hipStream_t s, bool adjoint = false) {
+    int64_t stride[4];
+    step_strides(st, axis, stride);
+    if (!adjoint) mark(st, VP_TIMER_SWEEP_X1 + axis, s);
     vp_status rc = st->method == 0
                        ? sldg_advect_impl(axis, st->degree, st->dt, st->dims, in, out,
-                                          shift, stride, s)
+                                          shift, stride, s, adjoint)
                        : spline_advect_impl(axis, st->dt, st->dims, in, out, shift,
-                                            stride, s);
-    mark(st, VP_TIMER_SWEEP_X1 + axis, s);
+                                            stride, s, adjoint);
+    if (!adjoint) mark(st, VP_TIMER_SWEEP_X1 + axis, s);
     return rc;
 }
+
+vp_status dshift(vp_state* st, int axis, const void* f, const void* lam,
+                 const double* shift, double* g_line, hipStream_t s) {
+    int64_t stride[4];
+    step_strides(st, axis, stride);
+    return st->method == 0
+               ? sldg_dshift_impl(axis, st->degree, st->dt, st->dims, f, lam, shift, stride,
+                                  g_line, s)
+               : spline_dshift_impl(axis, st->dt, st->dims, f, lam, shift, stride, g_line, s);
+}
+
+size_t f_bytes(const vp_state* st) {
+    return static_cast<size_t>(st->dims[0] * st->dims[1] * st->dims[2] * st->dims[3]) *
+           dtype_size(st->dt);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // W (and optionally the moments) of the state in f.
 vp_status diagnostics(vp_state* st, const void* f, double* W, double* mom,
@@ -146,7 +171,7 @@ extern "C" vp_status vp_create(vp_state** out, int method, int degree, vp_dtype 
     }
     const int64_t nx = dims[0] * dims[1];
     const size_t pws = vp_poisson_workspace(deg, dims[0], dims[1]);
-    const size_t ndbl = static_cast<size_t>(nx) * (5 + 4) +
+    const size_t ndbl = static_cast<size_t>(nx) * (5 + 4 + 3) +
                         2 * static_cast<size_t>(dims[2] + dims[3]) + pws / sizeof(double) + 64;
     void* mem = nullptr;
     hipError_t e = hipMalloc(&mem, ndbl * sizeof(double));
@@ -163,6 +188,9 @@ extern "C" vp_status vp_create(vp_state** out, int method, int degree, vp_dtype 
     st->sig_v1 = p; p += nx;
     st->sig_v2 = p; p += nx;
     st->partial = p; p += 4 * nx;
+    st->gs1 = p; p += nx;
+    st->gs2 = p; p += nx;
+    st->rho_bar = p; p += nx;
     st->sig_x1 = p; p += dims[2];
     st->sig_x2 = p; p += dims[3];
     st->vnode1 = p; p += dims[2];
@@ -285,4 +313,106 @@ extern "C" vp_status vp_timing_read(vp_state* st, double* ms, int64_t* counts) {
         v.clear();
     }
     return VP_OK;
+}
+
+extern "C" size_t vp_strang_adjoint_workspace(const vp_state* st) {
+    if (!st) return 0;
+    const int64_t nv = st->dims[2] > st->dims[3] ? st->dims[2] : st->dims[3];
+    return 3 * align256(f_bytes(st)) +
+           sizeof(double) * static_cast<size_t>(st->dims[0] * st->dims[1] * nv);
+}
+
+extern "C" vp_status vp_strang_adjoint(vp_state* st, const void* f, void* lam, double tau,
+                                       void* work, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (!st || !f || !lam || !work) return set_error(VP_ERR_ARG, "NULL pointer argument");
+    if (!(tau == tau) || tau > 1e300 || tau < -1e300) return set_error(VP_ERR_ARG, "tau not finite");
+    if (ws_bytes < vp_strang_adjoint_workspace(st))
+        return set_error(VP_ERR_WORKSPACE, "workspace of %zu bytes needed",
+                         vp_strang_adjoint_workspace(st));
+    const size_t fb = f_bytes(st);
+    if (ranges_overlap(f, lam, fb)) return set_error(VP_ERR_ALIAS, "f and lam overlap");
+    if (ranges_overlap(f, work, vp_strang_adjoint_workspace(st)) ||
+        ranges_overlap(lam, work, vp_strang_adjoint_workspace(st)))
+        return set_error(VP_ERR_ALIAS, "workspace overlaps f or lam");
+    int cur = -1;
+    VP_HIP_TRY(hipGetDevice(&cur));
+    if (cur != st->device)
+        return set_error(VP_ERR_ARG, "state belongs to device %d, current device is %d",
+                         st->device, cur);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned char* w = static_cast<unsigned char*>(work);
+    void* bufA = w;
+    void* bufB = w + align256(fb);
+    void* bufC = w + 2 * align256(fb);
+    double* gline = reinterpret_cast<double*>(w + 3 * align256(fb));
+    const int64_t nx = st->dims[0] * st->dims[1];
+    vp_status rc;
+
+    const int64_t nv = st->dims[2] > st->dims[3] ? st->dims[2] : st->dims[3];
+    xshift<<<blocks_for(nv, 256), 256, 0, s>>>(st->vnode1, st->vnode2, st->dims[2],
+                                               st->dims[3], 0.5 * tau / st->h[0],
+                                               0.5 * tau / st->h[1], st->sig_x1,
+                                               st->sig_x2);
+    if ((rc = check_launch("xshift")) != VP_OK) return rc;
+    // recompute the states the backward pass needs: f2 (bufB), f3 (bufA)
+    if ((rc = sweep(st, 0, f, bufA, st->sig_x1, s)) != VP_OK) return rc;
+    if ((rc = sweep(st, 1, bufA, bufB, st->sig_x2, s)) != VP_OK) return rc;
+    rc = density_impl(st->degree, st->dt, st->dims, bufB, st->len[2], st->len[3], st->rho, s);
+    if (rc == VP_OK)
+        rc = poisson_impl_shift(st->degree, st->dims[0], st->dims[1], st->len[0], st->len[1],
+                                st->rho, st->e1, st->e2, nullptr, st->pws, st->sig_v1,
+                                st->sig_v2, tau / st->h[2], tau / st->h[3], s);
+    if (rc != VP_OK) return rc;
+    if ((rc = sweep(st, 2, bufB, bufA, st->sig_v1, s)) != VP_OK) return rc;
+    // backward through x2, x1 (second half step)
+    if ((rc = sweep(st, 1, lam, bufC, st->sig_x2, s, true)) != VP_OK) return rc;
+    if ((rc = sweep(st, 0, bufC, lam, st->sig_x1, s, true)) != VP_OK) return rc;
+    // v2 sweep: shift gradient with f3, then transpose
+    if ((rc = dshift(st, 3, bufA, lam, st->sig_v2, gline, s)) != VP_OK) return rc;
+    if ((rc = line_sum_impl(gline, nx, static_cast<int>(st->dims[2]), tau / st->h[3], st->gs2,
+                            s)) != VP_OK)
+        return rc;
+    if ((rc = sweep(st, 3, lam, bufC, st->sig_v2, s, true)) != VP_OK) return rc;
+    // v1 sweep: shift gradient with f2, then transpose
+    if ((rc = dshift(st, 2, bufB, bufC, st->sig_v1, gline, s)) != VP_OK) return rc;
+    if ((rc = line_sum_impl(gline, nx, static_cast<int>(st->dims[3]), tau / st->h[2], st->gs1,
+                            s)) != VP_OK)
+        return rc;
+    if ((rc = sweep(st, 2, bufC, lam, st->sig_v1, s, true)) != VP_OK) return rc;
+    // field: dJ/dE -> rho_bar -> density transpose, added to the adjoint of f2
+    rc = poisson_adjoint_impl(st->degree, st->dims[0], st->dims[1], st->len[0], st->len[1],
+                              st->gs1, st->gs2, st->rho_bar, st->pws, false, s);
+    if (rc == VP_OK)
+        rc = density_adjoint_impl(st->degree, st->dt, st->dims, st->rho_bar, st->len[2],
+                                  st->len[3], lam, true, s);
+    if (rc != VP_OK) return rc;
+    // backward through x2, x1 (first half step)
+    if ((rc = sweep(st, 1, lam, bufC, st->sig_x2, s, true)) != VP_OK) return rc;
+    return sweep(st, 0, bufC, lam, st->sig_x1, s, true);
+}
+
+extern "C" vp_status vp_energy_gradient(vp_state* st, const void* f, void* lam, double* W,
+                                        void* stream) {
+    clear_error();
+    if (!st || !f || !lam) return set_error(VP_ERR_ARG, "NULL pointer argument");
+    if (ranges_overlap(f, lam, f_bytes(st))) return set_error(VP_ERR_ALIAS, "f and lam overlap");
+    int cur = -1;
+    VP_HIP_TRY(hipGetDevice(&cur));
+    if (cur != st->device)
+        return set_error(VP_ERR_ARG, "state belongs to device %d, current device is %d",
+                         st->device, cur);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    vp_status rc = density_impl(st->degree, st->dt, st->dims, f, st->len[2], st->len[3],
+                                st->rho, s);
+    if (rc == VP_OK)
+        rc = poisson_impl(st->degree, st->dims[0], st->dims[1], st->len[0], st->len[1], st->rho,
+                          st->e1, st->e2, W, st->pws, s);
+    if (rc == VP_OK)
+        rc = poisson_adjoint_impl(st->degree, st->dims[0], st->dims[1], st->len[0], st->len[1],
+                                  st->e1, st->e2, st->rho_bar, st->pws, true, s);
+    if (rc == VP_OK)
+        rc = density_adjoint_impl(st->degree, st->dt, st->dims, st->rho_bar, st->len[2],
+                                  st->len[3], lam, false, s);
+    return rc;
 }
