@@ -67,9 +67,13 @@ vp_status check_shift_strides(int axis, const int64_t dims[4],
 }
 
 bool ranges_overlap(const void* a, const void* b, size_t bytes) {
+    return ranges_overlap2(a, bytes, b, bytes);
+}
+
+bool ranges_overlap2(const void* a, size_t na, const void* b, size_t nb) {
     const uintptr_t x = reinterpret_cast<uintptr_t>(a);
     const uintptr_t y = reinterpret_cast<uintptr_t>(b);
-    return x < y + bytes && y < x + bytes;
+    return x < y + nb && y < x + na;
 }
 
 ShiftMap make_shift_map(int axis, const int64_t dims[4], const int64_t stride[4]) {

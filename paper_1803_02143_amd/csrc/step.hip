@@ -332,8 +332,8 @@ extern "C" vp_status vp_strang_adjoint(vp_state* st, const void* f, void* lam, d
                          vp_strang_adjoint_workspace(st));
     const size_t fb = f_bytes(st);
     if (ranges_overlap(f, lam, fb)) return set_error(VP_ERR_ALIAS, "f and lam overlap");
-    if (ranges_overlap(f, work, vp_strang_adjoint_workspace(st)) ||
-        ranges_overlap(lam, work, vp_strang_adjoint_workspace(st)))
+    const size_t wb = vp_strang_adjoint_workspace(st);
+    if (ranges_overlap2(f, fb, work, wb) || ranges_overlap2(lam, fb, work, wb))
         return set_error(VP_ERR_ALIAS, "workspace overlaps f or lam");
     int cur = -1;
     VP_HIP_TRY(hipGetDevice(&cur));

@@ -57,6 +57,8 @@ vp_status check_dims(const int64_t dims[4], int64_t* total);
 vp_status check_shift_strides(int axis, const int64_t dims[4],
                               const int64_t stride[4]);
 bool ranges_overlap(const void* a, const void* b, size_t bytes);
+// [a, a+na) and [b, b+nb) intersect
+bool ranges_overlap2(const void* a, size_t na, const void* b, size_t nb);
 
 inline size_t dtype_size(vp_dtype dt) { return dt == VP_F64 ? 8 : 4; }
 
