@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--no-other-precision", action="store_true",
                     help="skip the second timed run in the other storage precision")
     ap.add_argument("--methods", default="sldg,spline")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the timing of the adjoint step and its kernels")
+    ap.add_argument("--adjoint-steps", type=int, default=20)
     ap.add_argument("--copy-ref", type=int, default=0,
                     help="plain device copies of one f buffer before the run (a "
                          "reference kernel of known size for hardware counters)")
@@ -153,6 +156,107 @@ def run_precision(vp, torch, w, dt, methods, steps, warmup, stream, copy_ref=0):
     return elapsed, runs
 
 
+def _event_ms(torch, stream, fn, reps):
+    """Average milliseconds of `fn()` over `reps` calls, HIP events recorded
+    on the stream the library launches on."""
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    fn()
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def step_shifts(w, degree):
+    """The shifts (in cells or grid points) of the first Strang step of the
+    Landau run: x sweeps (tau/2) v / h_x at the velocity nodes, v sweeps
+    tau E / h_v with the field of the initial perturbation,
+    E_d = (eps / k) sin(k x_d)."""
+    import numpy as np
+
+    m = 1 if degree < 0 else degree + 1
+    if degree < 0:
+        xi = np.array([0.5])
+    else:
+        xi = (np.polynomial.legendre.leggauss(m)[0] + 1.0) / 2.0
+    nodes, h = [], []
+    for d in range(4):
+        nc = w.dofs[d] // m
+        hd = w.length[d] / nc
+        nodes.append(w.lo[d] + (np.arange(nc)[:, None] + xi[None, :]).ravel() * hd)
+        h.append(hd)
+    out = []
+    for axis in range(4):
+        shape = [1, 1, 1, 1]
+        if axis < 2:
+            shape[axis + 2] = w.dofs[axis + 2]
+            sig = 0.5 * w.dt * nodes[axis + 2] / h[axis]
+        else:
+            shape[0], shape[1] = w.dofs[0], w.dofs[1]
+            x = nodes[axis - 2]
+            e = (w.eps / w.k) * np.sin(w.k * x)
+            sig = w.dt * e / h[axis]
+            sig = sig[:, None] if axis == 2 else sig[None, :]
+            sig = np.broadcast_to(sig, (w.dofs[0], w.dofs[1]))
+        out.append(np.ascontiguousarray(np.asarray(sig, dtype=np.float64).reshape(shape)))
+    return out
+
+
+def run_adjoint(vp, torch, w, dt, methods, steps, stream):
+    """Reverse-mode cost on the same grid: whole adjoint Strang steps
+    (recompute of the forward half step, six transposed sweeps, two shift
+    derivatives, the field transposes), and each transposed sweep and shift
+    derivative on its own with the shifts of the step."""
+    import numpy as np
+
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    esize = 8 if dt == "f64" else 4
+    dims = w.dofs
+    n4 = int(np.prod(dims))
+    out = {}
+    for m in methods:
+        method = vp.METHOD_SLDG if m == "sldg" else vp.METHOD_SPLINE
+        deg = w.degree if m == "sldg" else -1
+        st = vp.VPState(method, w.degree, tdt, dims, w.lo, w.length)
+        f = torch.empty(dims, dtype=tdt, device="cuda")
+        vp.vp_init(vp.IC_LANDAU if w.ic == "landau" else vp.IC_TWO_STREAM_SUM,
+                   w.eps, w.k, w.v0, deg, f, w.lo, w.length)
+        lam = torch.empty_like(f)
+        st.energy_gradient(f, lam, None, stream)
+        work = st.adjoint_workspace()
+        ms_step = _event_ms(torch, stream, lambda: st.adjoint_step(f, lam, w.dt, work, stream),
+                            steps)
+        res = {"ms_per_adjoint_step": ms_step, "kernels": {}}
+        # per-axis kernels with the shifts of the first step
+        buf = torch.empty_like(f)
+        shifts = step_shifts(w, deg)
+        for axis in range(4):
+            sig = torch.from_numpy(shifts[axis]).cuda()
+            g = torch.empty(n4 // dims[axis], dtype=torch.float64, device="cuda")
+            if m == "sldg":
+                adj = lambda: vp.sldg_advect_adjoint(axis, w.degree, buf, lam, sig, stream=stream)
+                dsh = lambda: vp.sldg_advect_dshift(axis, w.degree, f, lam, sig, g, stream=stream)
+            else:
+                adj = lambda: vp.spline_advect_adjoint(axis, buf, lam, sig, stream=stream)
+                dsh = lambda: vp.spline_advect_dshift(axis, f, lam, sig, g, stream=stream)
+            name = ("x1", "x2", "v1", "v2")[axis]
+            for kind, fn in (("adjoint_sweep", adj), ("dshift", dsh)):
+                ms = _event_ms(torch, stream, fn, 10)
+                # adjoint sweep: read lam, write lam'; shift derivative: read f
+                # and lam, write one value per line
+                nbytes = 2 * n4 * esize + (8 * (n4 // dims[axis]) if kind == "dshift" else 0)
+                res["kernels"][f"{m}_{kind}_{name}"] = {
+                    "avg_ms": ms, "alg_GBs": nbytes / (ms * 1e-3) / 1e9}
+        st.close()
+        out[m] = res
+        del f, lam, work, buf
+        torch.cuda.empty_cache()
+    return out
+
+
 def kernel_table(runs, n4, esize):
     """Per-kernel averages from the library's HIP events, and the sweep with
     the largest total time."""
@@ -232,6 +336,14 @@ def main():
         "W_el_last": W_last,
         "rel_mass_drift": mass_drift,
     }
+
+    if not a.no_adjoint:
+        adj = run_adjoint(vp, torch, w, dt, methods, a.adjoint_steps, stream)
+        for m, r in adj.items():
+            # forward step time of the method: its library timers per step
+            fwd = sum(v["total_ms"] for k, v in detail.items() if k.startswith(m + "_")) / a.steps
+            r["adjoint_over_forward_kernel_time"] = r["ms_per_adjoint_step"] / fwd
+        out["adjoint"] = adj
 
     if not a.no_other_precision:
         # the same steps in the other storage precision: its rates, and its

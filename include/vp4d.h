@@ -272,8 +272,11 @@ VP4D_API vp_status vp_energy_gradient(vp_state* st, const void* f, void* lam, do
  * from f = f^m (Sec. 2).  The step's internal states are recomputed from f;
  * the shift dependence of the acceleration sweeps on E(rho(f)) is carried
  * through the Poisson and density transposes.
- *   work  device, at least vp_strang_adjoint_workspace(st) bytes (three
- *         copies of f plus one double per velocity line).
+ *   work  device, at least vp_strang_adjoint_workspace(st) bytes: two
+ *         copies of f (each rounded up to 256 bytes) and one double per
+ *         line of the longer velocity axis, 8 N1 N2 max(N3, N4) bytes.
+ * f, lam and work must not overlap (VP_ERR_ALIAS); a workspace that is
+ * too small is VP_ERR_WORKSPACE.  Enqueued on `stream`, asynchronous.
  */
 VP4D_API size_t vp_strang_adjoint_workspace(const vp_state* st);
 VP4D_API vp_status vp_strang_adjoint(vp_state* st, const void* f, void* lam, double tau,

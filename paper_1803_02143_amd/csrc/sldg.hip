@@ -450,41 +450,90 @@ sldg_dshift_col(const T* __restrict__ fin, const T* __restrict__ lam,
     g[gid] = acc;
 }
 
-// Contiguous lines: one wavefront per line, lanes over output cells,
-// cross-lane reduction.
+// Contiguous lines: R lines per workgroup.  The lines' derivative operators
+// are built once per line into LDS; then one thread per output cell forms
+// lam_i . (A' u_{i-s-1} + B' u_{i-s}) with loads that neighbouring lanes
+// share, and each line's cell terms are summed from LDS.
 template <int M, typename T>
 __global__ void __launch_bounds__(kBlock)
 sldg_dshift_row(const T* __restrict__ fin, const T* __restrict__ lam,
                 const double* __restrict__ shift, ShiftMap sm, int64_t nrows,
-                int nc, NodeBasis basis, double* __restrict__ g) {
-    const int lane = threadIdx.x & 63;
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
-    if (row >= nrows) return;
-    int s;
-    T dA[M][M], dB[M][M];
-    sldg_operator_deriv<M, T>(basis, shift[shift_offset(sm, row, 0)], nc, s, dA, dB);
+                int nc, int R, NodeBasis basis, double* __restrict__ g) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* part = reinterpret_cast<double*>(smem);           // R * nc cell terms
+    T* ops = reinterpret_cast<T*>(part + R * nc);              // R * 2 M^2
+    int* sh = reinterpret_cast<int*>(ops + R * 2 * M * M);     // R
+    const int64_t row0 = static_cast<int64_t>(blockIdx.x) * R;
+    const int nr = static_cast<int>(min(static_cast<int64_t>(R), nrows - row0));
+    for (int r = threadIdx.x; r < nr; r += kBlock) {
+        int s;
+        T dA[M][M], dB[M][M];
+        sldg_operator_deriv<M, T>(basis, shift[shift_offset(sm, row0 + r, 0)], nc, s, dA, dB);
+        T* op = ops + r * 2 * M * M;
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                op[j * M + l] = dA[j][l];
+                op[M * M + j * M + l] = dB[j][l];
+            }
+        sh[r] = s;
+    }
+    __syncthreads();
     const int N = nc * M;
-    const T* __restrict__ u = fin + row * N;
-    const T* __restrict__ lr = lam + row * N;
-    double acc = 0.0;
-    for (int i = lane; i < nc; i += 64) {
-        int left = i - s - 1;
-        if (left < 0) left += nc;
-        int right = left + 1;
-        if (right >= nc) right -= nc;
+    const int ncell = nr * nc;
+    const T* __restrict__ u0 = fin + row0 * N;
+    const T* __restrict__ l0 = lam + row0 * N;
+    constexpr int kB = 4;  // cells per thread whose loads are in flight together
+    for (int q0 = threadIdx.x; q0 < ncell; q0 += kB * kBlock) {
+        T ul[kB][M], ur[kB][M], lv[kB][M];
+        int qq[kB];
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-            T d = T(0);
+        for (int b = 0; b < kB; ++b) {
+            const int q = min(q0 + b * kBlock, ncell - 1);
+            const int r = q / nc;
+            const int i = q - r * nc;
+            int left = i - sh[r] - 1;
+            left += left < 0 ? nc : 0;
+            int right = left + 1;
+            right -= right >= nc ? nc : 0;
+            qq[b] = q;
 #pragma unroll
-            for (int l = 0; l < M; ++l) d = fma(dA[j][l], u[left * M + l], d);
+            for (int l = 0; l < M; ++l) {
+                ul[b][l] = u0[r * N + left * M + l];
+                ur[b][l] = u0[r * N + right * M + l];
+                lv[b][l] = l0[q * M + l];
+            }
+        }
 #pragma unroll
-            for (int l = 0; l < M; ++l) d = fma(dB[j][l], u[right * M + l], d);
-            acc = fma(static_cast<double>(lr[i * M + j]), static_cast<double>(d), acc);
+        for (int b = 0; b < kB; ++b) {
+            const int q = qq[b];
+            const T* op = ops + (q / nc) * 2 * M * M;
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                T d = T(0);
+#pragma unroll
+                for (int l = 0; l < M; ++l) d = fma(op[j * M + l], ul[b][l], d);
+#pragma unroll
+                for (int l = 0; l < M; ++l) d = fma(op[M * M + j * M + l], ur[b][l], d);
+                acc = fma(static_cast<double>(lv[b][j]), static_cast<double>(d), acc);
+            }
+            if (q0 + b * kBlock < ncell) part[q] = acc;
         }
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) g[row] = acc;
+    __syncthreads();
+    // per-line sums; the start is skewed by the line index so that the
+    // threads of a wavefront read different LDS banks
+    for (int r = threadIdx.x; r < nr; r += kBlock) {
+        double acc = 0.0;
+        int c = r % nc;
+        for (int k = 0; k < nc; ++k) {
+            acc += part[r * nc + c];
+            c = c + 1 == nc ? 0 : c + 1;
+        }
+        g[row0 + r] = acc;
+    }
 }
 
 template <int M, typename T>
@@ -506,8 +555,18 @@ vp_status launch_dshift(int axis, const int64_t dims[4], const void* fin, const 
         }
         return check_launch("sldg_dshift_col");
     }
-    sldg_dshift_row<M, T><<<blocks_for(outer, kBlock / 64), kBlock, 0, st>>>(in, l, shift, sm,
-                                                                             outer, nc, b, g);
+    // lines per workgroup: about 2048 cells, at most 48 KiB of LDS
+    const size_t per_row = static_cast<size_t>(nc) * sizeof(double) +
+                           static_cast<size_t>(2 * M * M) * sizeof(T) + sizeof(int);
+    int R = 2048 / nc;
+    if (R < 1) R = 1;
+    if (R > kBlock) R = kBlock;
+    while (R > 1 && R * per_row > 48 * 1024) R /= 2;
+    const size_t lds = R * per_row;
+    if (lds > 64 * 1024)
+        return set_error(VP_ERR_UNSUPPORTED, "sldg dshift: line of %d cells too long", nc);
+    sldg_dshift_row<M, T><<<blocks_for(outer, R), kBlock, lds, st>>>(in, l, shift, sm, outer,
+                                                                      nc, R, b, g);
     return check_launch("sldg_dshift_row");
 }
 

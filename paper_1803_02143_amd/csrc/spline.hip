@@ -313,6 +313,16 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         }
         for (; i < e; ++i) buf[i * L + l] = src[static_cast<int64_t>(i) * inner];
     }
+    // shift derivative: the thread's segment of lam, in flight during the
+    // solve (clamped indices, no branches between the loads)
+    constexpr int SM = SegMax<T>::value;
+    T lv[MODE == kDshift ? SM : 1];
+    if (MODE == kDshift && active) {
+        const T* __restrict__ lm = lam + base + l;
+#pragma unroll
+        for (int t = 0; t < SM; ++t)
+            lv[t] = lm[static_cast<int64_t>(min(b + t, e - 1)) * inner];
+    }
     int s = 0;
     T w0 = T(0), w1 = T(0), w2 = T(0), w3 = T(0);
     if (active) {
@@ -341,7 +351,6 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     if (active) {
         // sliding window over omega_{i-s-2 .. i-s+1}
         T* __restrict__ dst = fout + base + l;
-        const T* __restrict__ lm = lam + base + l;
         int j = first_tap(b, s, n);
         T c0 = buf[j * L + l];
         j = next_idx(j, n);
@@ -368,18 +377,29 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                 j = j7;
             }
         }
-        for (; i < e; ++i) {
-            const T v = fma(w3, c3, fma(w2, c2, fma(w1, c1, w0 * c0)));
-            if (MODE == kFwd)
-                dst[static_cast<int64_t>(i) * inner] = v;
-            else
-                acc = fma(static_cast<double>(lm[static_cast<int64_t>(i) * inner]),
-                          static_cast<double>(v), acc);
-            c0 = c1;
-            c1 = c2;
-            c2 = c3;
-            j = next_idx(j, n);
-            c3 = buf[j * L + l];
+        if (MODE == kFwd) {
+            for (; i < e; ++i) {
+                dst[static_cast<int64_t>(i) * inner] =
+                    fma(w3, c3, fma(w2, c2, fma(w1, c1, w0 * c0)));
+                c0 = c1;
+                c1 = c2;
+                c2 = c3;
+                j = next_idx(j, n);
+                c3 = buf[j * L + l];
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < SM; ++t) {
+                if (b + t < e) {
+                    const T v = fma(w3, c3, fma(w2, c2, fma(w1, c1, w0 * c0)));
+                    acc = fma(static_cast<double>(lv[t]), static_cast<double>(v), acc);
+                    c0 = c1;
+                    c1 = c2;
+                    c2 = c3;
+                    j = next_idx(j, n);
+                    c3 = buf[j * L + l];
+                }
+            }
         }
     }
     if (MODE == kDshift) {
@@ -464,7 +484,7 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                                active);
         spline_solve_segment<T>(buf + r * ld, 1, b, e, active, sp);
     }
-    for (int r = wave; r < nr; r += kWaves) {
+    for (int r = wave; MODE != kDshift && r < nr; r += kWaves) {
         const T* row = buf + r * ld;
         T* __restrict__ dst = fout + (row0 + r) * n;
         if (MODE == kAdj) {
@@ -474,20 +494,51 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         const T w0 = wts[4 * r + 0], w1 = wts[4 * r + 1];
         const T w2 = wts[4 * r + 2], w3 = wts[4 * r + 3];
         const int s = sh[r];
-        double acc = 0.0;
         for (int i = lane; i < n; i += 64) {
             const int j0 = first_tap(i, s, n);
             const int j1 = next_idx(j0, n), j2 = next_idx(j1, n), j3 = next_idx(j2, n);
-            const T v = fma(w3, row[j3], fma(w2, row[j2], fma(w1, row[j1], w0 * row[j0])));
-            if (MODE == kFwd)
-                dst[i] = v;
-            else
-                acc = fma(static_cast<double>(lam[(row0 + r) * n + i]), static_cast<double>(v), acc);
+            dst[i] = fma(w3, row[j3], fma(w2, row[j2], fma(w1, row[j1], w0 * row[j0])));
         }
-        if (MODE == kDshift) {
+    }
+    if (MODE != kDshift) return;
+    // shift derivative: kU rows per wavefront at a time, their lam loads
+    // issued back to back (clamped indices), one FP64 sum per row
+    for (int r0 = wave; r0 < nr; r0 += kWaves * kU) {
+        double acc[kU];
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-            if (lane == 0) g[row0 + r] = acc;
+        for (int u = 0; u < kU; ++u) acc[u] = 0.0;
+        for (int i0 = 0; i0 < n; i0 += 64) {
+            const int i = i0 + lane;
+            const int ic = i < n ? i : n - 1;
+            T lv[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int r = r0 + u * kWaves;
+                lv[u] = lam[(row0 + (r < nr ? r : nr - 1)) * n + ic];
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int r = r0 + u * kWaves;
+                if (r < nr && i < n) {
+                    const T* row = buf + r * ld;
+                    const int s = sh[r];
+                    const int j0 = first_tap(i, s, n);
+                    const int j1 = next_idx(j0, n), j2 = next_idx(j1, n);
+                    const int j3 = next_idx(j2, n);
+                    const T v = fma(wts[4 * r + 3], row[j3],
+                                    fma(wts[4 * r + 2], row[j2],
+                                        fma(wts[4 * r + 1], row[j1], wts[4 * r] * row[j0])));
+                    acc[u] = fma(static_cast<double>(lv[u]), static_cast<double>(v), acc[u]);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            double a = acc[u];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+            const int r = r0 + u * kWaves;
+            if (lane == 0 && r < nr) g[row0 + r] = a;
         }
     }
 }

@@ -318,7 +318,7 @@ extern "C" vp_status vp_timing_read(vp_state* st, double* ms, int64_t* counts) {
 extern "C" size_t vp_strang_adjoint_workspace(const vp_state* st) {
     if (!st) return 0;
     const int64_t nv = st->dims[2] > st->dims[3] ? st->dims[2] : st->dims[3];
-    return 3 * align256(f_bytes(st)) +
+    return 2 * align256(f_bytes(st)) +
            sizeof(double) * static_cast<size_t>(st->dims[0] * st->dims[1] * nv);
 }
 
@@ -341,11 +341,12 @@ extern "C" vp_status vp_strang_adjoint(vp_state* st, const void* f, void* lam, d
         return set_error(VP_ERR_ARG, "state belongs to device %d, current device is %d",
                          st->device, cur);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // two state-sized buffers: P holds f2, Q holds f1, then f3, then the
+    // adjoint between the v2 and v1 transposes
     unsigned char* w = static_cast<unsigned char*>(work);
-    void* bufA = w;
-    void* bufB = w + align256(fb);
-    void* bufC = w + 2 * align256(fb);
-    double* gline = reinterpret_cast<double*>(w + 3 * align256(fb));
+    void* bufP = w;
+    void* bufQ = w + align256(fb);
+    double* gline = reinterpret_cast<double*>(w + 2 * align256(fb));
     const int64_t nx = st->dims[0] * st->dims[1];
     vp_status rc;
 
@@ -355,31 +356,31 @@ extern "C" vp_status vp_strang_adjoint(vp_state* st, const void* f, void* lam, d
                                                0.5 * tau / st->h[1], st->sig_x1,
                                                st->sig_x2);
     if ((rc = check_launch("xshift")) != VP_OK) return rc;
-    // recompute the states the backward pass needs: f2 (bufB), f3 (bufA)
-    if ((rc = sweep(st, 0, f, bufA, st->sig_x1, s)) != VP_OK) return rc;
-    if ((rc = sweep(st, 1, bufA, bufB, st->sig_x2, s)) != VP_OK) return rc;
-    rc = density_impl(st->degree, st->dt, st->dims, bufB, st->len[2], st->len[3], st->rho, s);
+    // backward through x2, x1 of the second half step (Q is still free)
+    if ((rc = sweep(st, 1, lam, bufQ, st->sig_x2, s, true)) != VP_OK) return rc;
+    if ((rc = sweep(st, 0, bufQ, lam, st->sig_x1, s, true)) != VP_OK) return rc;
+    // recompute the states the shift derivatives need: f2 (P), f3 (Q)
+    if ((rc = sweep(st, 0, f, bufQ, st->sig_x1, s)) != VP_OK) return rc;
+    if ((rc = sweep(st, 1, bufQ, bufP, st->sig_x2, s)) != VP_OK) return rc;
+    rc = density_impl(st->degree, st->dt, st->dims, bufP, st->len[2], st->len[3], st->rho, s);
     if (rc == VP_OK)
         rc = poisson_impl_shift(st->degree, st->dims[0], st->dims[1], st->len[0], st->len[1],
                                 st->rho, st->e1, st->e2, nullptr, st->pws, st->sig_v1,
                                 st->sig_v2, tau / st->h[2], tau / st->h[3], s);
     if (rc != VP_OK) return rc;
-    if ((rc = sweep(st, 2, bufB, bufA, st->sig_v1, s)) != VP_OK) return rc;
-    // backward through x2, x1 (second half step)
-    if ((rc = sweep(st, 1, lam, bufC, st->sig_x2, s, true)) != VP_OK) return rc;
-    if ((rc = sweep(st, 0, bufC, lam, st->sig_x1, s, true)) != VP_OK) return rc;
-    // v2 sweep: shift gradient with f3, then transpose
-    if ((rc = dshift(st, 3, bufA, lam, st->sig_v2, gline, s)) != VP_OK) return rc;
+    if ((rc = sweep(st, 2, bufP, bufQ, st->sig_v1, s)) != VP_OK) return rc;
+    // v2 sweep: shift gradient with f3, then the transpose overwrites f3
+    if ((rc = dshift(st, 3, bufQ, lam, st->sig_v2, gline, s)) != VP_OK) return rc;
     if ((rc = line_sum_impl(gline, nx, static_cast<int>(st->dims[2]), tau / st->h[3], st->gs2,
                             s)) != VP_OK)
         return rc;
-    if ((rc = sweep(st, 3, lam, bufC, st->sig_v2, s, true)) != VP_OK) return rc;
-    // v1 sweep: shift gradient with f2, then transpose
-    if ((rc = dshift(st, 2, bufB, bufC, st->sig_v1, gline, s)) != VP_OK) return rc;
+    if ((rc = sweep(st, 3, lam, bufQ, st->sig_v2, s, true)) != VP_OK) return rc;
+    // v1 sweep: shift gradient with f2, then transpose back into lam
+    if ((rc = dshift(st, 2, bufP, bufQ, st->sig_v1, gline, s)) != VP_OK) return rc;
     if ((rc = line_sum_impl(gline, nx, static_cast<int>(st->dims[3]), tau / st->h[2], st->gs1,
                             s)) != VP_OK)
         return rc;
-    if ((rc = sweep(st, 2, bufC, lam, st->sig_v1, s, true)) != VP_OK) return rc;
+    if ((rc = sweep(st, 2, bufQ, lam, st->sig_v1, s, true)) != VP_OK) return rc;
     // field: dJ/dE -> rho_bar -> density transpose, added to the adjoint of f2
     rc = poisson_adjoint_impl(st->degree, st->dims[0], st->dims[1], st->len[0], st->len[1],
                               st->gs1, st->gs2, st->rho_bar, st->pws, false, s);
@@ -387,9 +388,9 @@ extern "C" vp_status vp_strang_adjoint(vp_state* st, const void* f, void* lam, d
         rc = density_adjoint_impl(st->degree, st->dt, st->dims, st->rho_bar, st->len[2],
                                   st->len[3], lam, true, s);
     if (rc != VP_OK) return rc;
-    // backward through x2, x1 (first half step)
-    if ((rc = sweep(st, 1, lam, bufC, st->sig_x2, s, true)) != VP_OK) return rc;
-    return sweep(st, 0, bufC, lam, st->sig_x1, s, true);
+    // backward through x2, x1 of the first half step
+    if ((rc = sweep(st, 1, lam, bufP, st->sig_x2, s, true)) != VP_OK) return rc;
+    return sweep(st, 0, bufP, lam, st->sig_x1, s, true);
 }
 
 extern "C" vp_status vp_energy_gradient(vp_state* st, const void* f, void* lam, double* W,

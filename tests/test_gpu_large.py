@@ -98,3 +98,78 @@ def test_capacity_run_288_f32_conserves_mass():
     st.close()
     del f, tmp
     torch.cuda.empty_cache()
+
+
+def test_capacity_run_288_f32_with_adjoint_tail():
+    # 100 FP32 Strang steps of the 288^4 workload, then dW(f^100)/df^80
+    # through the last 20 steps with checkpoints every 4 steps and every
+    # state recomputed from its checkpoint (at most 9 copies of f, 248 GB).
+    # The directional derivative along the perturbation mode is checked
+    # against FP64 central differences of the 20 steps from the same f^80.
+    vp = require_gpu()
+    import time
+    from paper_1803_02143_amd.autograd import final_electric_energy
+    w = workload("two_stream_96")
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
+    nb = int(np.prod(w.dofs)) * 4
+    announce(f"two_stream_96 f32: 80 Strang steps ({nb / 1e9:.1f} GB per copy)")
+    st = vp.VPState(vp.METHOD_SLDG, w.degree, torch.float32, w.dofs, w.lo, w.length)
+    f = torch.empty(w.dofs, dtype=torch.float32, device="cuda")
+    tmp = torch.empty_like(f)
+    vp.vp_init(vp.IC_TWO_STREAM_SUM, w.eps, w.k, w.v0, w.degree, f, w.lo, w.length)
+    mom = torch.empty(4 * 81, dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    st.step(f, tmp, 80, w.dt, None, mom)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    del tmp
+    m = mom.cpu().numpy().reshape(81, 4)
+    assert np.max(np.abs(m[:, 0] - m[0, 0])) <= 1e-5 * m[0, 0]
+
+    announce("two_stream_96 f32: last 20 steps with checkpoints, adjoint")
+    f80 = f.requires_grad_(True)
+    t0 = time.perf_counter()
+    J = final_electric_energy(f80, st, 20, w.dt, every=4, store_segment=False)
+    J.backward()
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    peak = torch.cuda.max_memory_allocated()
+    announce(f"80 steps {t_fwd:.2f} s; 20 steps + adjoint {t_adj:.2f} s; "
+             f"peak {peak / 1e9:.1f} GB ({peak / nb:.2f} copies of f)")
+    assert peak <= 9.2 * nb
+    grad = f80.grad.detach()
+    f80 = f80.detach()
+    del f
+    # perturbation direction d f0 / d eps, and the directional derivative
+    delta = torch.empty_like(f80)
+    vp.vp_init(vp.IC_TWO_STREAM_SUM, 1.0, w.k, w.v0, w.degree, delta, w.lo, w.length)
+    base = torch.empty_like(f80)
+    vp.vp_init(vp.IC_TWO_STREAM_SUM, 0.0, w.k, w.v0, w.degree, base, w.lo, w.length)
+    delta.sub_(base)
+    del base
+    g_dir = float(sum((grad[i].double() * delta[i].double()).sum() for i in range(w.dofs[0])))
+    del grad
+    torch.cuda.empty_cache()
+
+    announce("two_stream_96 f64: central differences over the last 20 steps")
+    st64 = vp.VPState(vp.METHOD_SLDG, w.degree, torch.float64, w.dofs, w.lo, w.length)
+    h = 1e-5
+    Js = []
+    for sgn in (1.0, -1.0):
+        g64 = f80.double()
+        g64.add_(delta.double(), alpha=sgn * h)
+        t64 = torch.empty_like(g64)
+        W = torch.empty(21, dtype=torch.float64, device="cuda")
+        st64.step(g64, t64, 20, w.dt, W)
+        Js.append(float(W[-1]))
+        del g64, t64
+        torch.cuda.empty_cache()
+    fd = (Js[0] - Js[1]) / (2 * h)
+    announce(f"adjoint {g_dir:.10e} vs central difference {fd:.10e}: "
+             f"rel {abs(g_dir - fd) / abs(fd):.2e}; W(f^100) = {J.item():.6e}")
+    assert abs(g_dir - fd) <= 1e-6 * abs(fd)
+    st.close()
+    st64.close()
+    del f80, delta
+    torch.cuda.empty_cache()
