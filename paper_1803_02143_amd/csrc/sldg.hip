@@ -17,9 +17,10 @@
 //    along the fastest axis.  Each input cell is loaded exactly once: the
 //    last cell is loaded first (it is the left neighbour of cell 0) and
 //    reused at the end.
-//  * sldg_row  -- the contiguous axis (v2).  A workgroup stages R whole
-//    lines in LDS with contiguous loads, builds the R line operators once,
-//    and every thread produces one output cell from two LDS cells.
+//  * sldg_row  -- the contiguous axis (v2).  A workgroup builds the
+//    operators of R whole lines once, into LDS; every thread then produces
+//    one output cell from its two input cells, which neighbouring lanes
+//    share through the L1 cache.
 //
 // The transposed sweep (for reverse-mode differentiation) is the same
 // gather with the transposed operators and the opposite offset:
@@ -272,10 +273,8 @@ sldg_row(const T* __restrict__ fin, T* __restrict__ fout,
          const double* __restrict__ shift, ShiftMap sm, int64_t nrows, int nc,
          int R, NodeBasis basis) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int N = nc * M;
-    T* tile = reinterpret_cast<T*>(smem);              // R * N
-    T* ops = tile + R * N;                             // R * 2 M^2
-    int* sh = reinterpret_cast<int*>(ops + R * 2 * M * M);
+    T* ops = reinterpret_cast<T*>(smem);                   // R * 2 M^2
+    int* sh = reinterpret_cast<int*>(ops + R * 2 * M * M);  // R
 
     const int64_t row0 = static_cast<int64_t>(blockIdx.x) * R;
     const int nr = static_cast<int>(min(static_cast<int64_t>(R), nrows - row0));
@@ -296,50 +295,56 @@ sldg_row(const T* __restrict__ fin, T* __restrict__ fout,
             }
         sh[r] = s;
     }
-    const int64_t base = row0 * N;
-    const int cnt = nr * N;
-    {
-        // batches of kU independent loads keep many requests in flight
-        int e = threadIdx.x;
-        for (; e + (kU - 1) * kBlock < cnt; e += kU * kBlock) {
-            T v[kU];
-#pragma unroll
-            for (int u = 0; u < kU; ++u) v[u] = fin[base + e + u * kBlock];
-#pragma unroll
-            for (int u = 0; u < kU; ++u) tile[e + u * kBlock] = v[u];
-        }
-        for (; e < cnt; e += kBlock) tile[e] = fin[base + e];
-    }
     __syncthreads();
 
+    // one thread per output cell; its two input cells come straight from
+    // global memory (neighbouring lanes share them in the L1 cache), kB
+    // cells' loads in flight together, clamped indices instead of branches
+    const int N = nc * M;
     const int ncell = nr * nc;
-    for (int q = threadIdx.x; q < ncell; q += kBlock) {
-        const int r = q / nc;
-        const int i = q - r * nc;
-        const int s = sh[r];
-        // forward: cells (i-s-1, i-s); transpose: cells (i+s, i+s+1)
-        int left = ADJ ? i + s : i - s - 1;
-        if (left < 0) left += nc;
-        if (left >= nc) left -= nc;
-        int right = left + 1;
-        if (right >= nc) right -= nc;
-        const T* op = ops + r * 2 * M * M;
-        const T* ul = tile + r * N + left * M;
-        const T* ur = tile + r * N + right * M;
-        T u0[M], u1[M];
+    const T* __restrict__ u0 = fin + row0 * N;
+    T* __restrict__ o0 = fout + row0 * N;
+    constexpr int kB = M <= 3 ? 4 : 2;
+    for (int q0 = threadIdx.x; q0 < ncell; q0 += kB * kBlock) {
+        T ul[kB][M], ur[kB][M];
+        int qq[kB];
 #pragma unroll
-        for (int l = 0; l < M; ++l) {
-            u0[l] = ul[l];
-            u1[l] = ur[l];
+        for (int b = 0; b < kB; ++b) {
+            const int q = min(q0 + b * kBlock, ncell - 1);
+            const int r = q / nc;
+            const int i = q - r * nc;
+            const int s = sh[r];
+            // forward: cells (i-s-1, i-s); transpose: cells (i+s, i+s+1)
+            int left = ADJ ? i + s : i - s - 1;
+            left += left < 0 ? nc : 0;
+            left -= left >= nc ? nc : 0;
+            int right = left + 1;
+            right -= right >= nc ? nc : 0;
+            qq[b] = q;
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                ul[b][l] = u0[r * N + left * M + l];
+                ur[b][l] = u0[r * N + right * M + l];
+            }
         }
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-            T acc = T(0);
+        for (int b = 0; b < kB; ++b) {
+            const int q = qq[b];
+            const T* op = ops + (q / nc) * 2 * M * M;
+            T out[M];
 #pragma unroll
-            for (int l = 0; l < M; ++l) acc = fma(op[j * M + l], u0[l], acc);
+            for (int j = 0; j < M; ++j) {
+                T acc = T(0);
 #pragma unroll
-            for (int l = 0; l < M; ++l) acc = fma(op[M * M + j * M + l], u1[l], acc);
-            fout[base + static_cast<int64_t>(r) * N + i * M + j] = acc;
+                for (int l = 0; l < M; ++l) acc = fma(op[j * M + l], ul[b][l], acc);
+#pragma unroll
+                for (int l = 0; l < M; ++l) acc = fma(op[M * M + j * M + l], ur[b][l], acc);
+                out[j] = acc;
+            }
+            if (q0 + b * kBlock < ncell) {
+#pragma unroll
+                for (int j = 0; j < M; ++j) o0[q * M + j] = out[j];
+            }
         }
     }
 }
@@ -370,18 +375,13 @@ vp_status launch_sldg(int axis, const int64_t dims[4], const void* fin,
         }
         return check_launch("sldg_col");
     }
-    const int N = static_cast<int>(dims[3]);
-    // rows per workgroup: about 4096 dofs, and at most 48 KiB of LDS
-    const size_t per_row = static_cast<size_t>(N) * sizeof(T) +
-                           static_cast<size_t>(2 * M * M) * sizeof(T) + sizeof(int);
-    int R = 4096 / N;
+    // rows per workgroup: one full round of the cell loop (4 or 2 cells per
+    // thread), the R operators in LDS
+    const size_t per_row = static_cast<size_t>(2 * M * M) * sizeof(T) + sizeof(int);
+    int R = (M <= 3 ? 4 : 2) * kBlock / nc;
     if (R < 1) R = 1;
     if (R > kBlock) R = kBlock;
-    while (R > 1 && R * per_row > 48 * 1024) R /= 2;
     const size_t lds = R * per_row;
-    if (lds > 64 * 1024)
-        return set_error(VP_ERR_UNSUPPORTED,
-                         "sldg_advect: line of %d dofs too long for the LDS tile", N);
     const unsigned grid = blocks_for(outer, R);
     sldg_row<M, T, ADJ><<<grid, kBlock, lds, st>>>(in, out, shift, sm, outer, nc, R, b);
     return check_launch("sldg_row");
