@@ -145,9 +145,14 @@ def run_precision(vp, torch, w, dt, methods, steps, warmup, stream, copy_ref=0):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for r in runs:
+        r["ev"] = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        r["ev"][0].record(stream)
         r["st"].step(r["f"], r["tmp"], steps, w.dt, r["W"], r["mom"], stream)
+        r["ev"][1].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    for r in runs:
+        r["ms_per_step"] = r["ev"][0].elapsed_time(r["ev"][1]) / steps
     for r in runs:
         r["timers"] = r["st"].timing_read()
         r["st"].timing_enable(False)
@@ -332,10 +337,24 @@ def main():
                                f"on {dims[0]}^4 points, dt={w.dt}",
                    "dofs": list(dims), "methods": methods, "sweeps_per_step": sweeps},
         "roofline": roofline,
+        "ms_per_step_by_method": {r["name"]: r["ms_per_step"] for r in runs},
         "kernels": detail,
         "W_el_last": W_last,
         "rel_mass_drift": mass_drift,
     }
+
+    if w.name.startswith("landau_table1_"):
+        # the paper's Table 1 (whole Strang steps, FP64 assumed, 16 threads
+        # on two Xeon E5-2630 v3 / one VSC3 node of two E5-2650 v2): context
+        paper = {64: {"sldg_dG4": (0.105, 0.151), "selalib_spline": (0.194, 0.219)},
+                 128: {"sldg_dG4": (1.62, 2.31), "selalib_spline": (3.25, 4.02)}}[dims[0]]
+        out["paper_table1"] = {
+            "dofs_per_direction": dims[0],
+            "this_run_s_per_step": {r["name"]: r["ms_per_step"] * 1e-3 for r in runs},
+            "paper_s_per_step": {k: {"workstation_2x_E5-2630v3": v[0],
+                                     "vsc3_node_2x_E5-2650v2": v[1]}
+                                 for k, v in paper.items()},
+        }
 
     if not a.no_adjoint:
         adj = run_adjoint(vp, torch, w, dt, methods, a.adjoint_steps, stream)

@@ -169,7 +169,7 @@ def test_nonfinite_shift_gives_nan_line_only():
 
 # --------------------------------------------------------- field kernels ---
 
-@pytest.mark.parametrize("degree", [2, 1, -1])
+@pytest.mark.parametrize("degree", [2, 1, 3, 5, -1])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_density_and_moments_parity(degree, dt):
     vp = require_gpu()
@@ -195,7 +195,8 @@ def test_density_and_moments_parity(degree, dt):
 
 
 @pytest.mark.parametrize("degree,n1,n2", [(2, 24, 18), (1, 10, 16), (-1, 32, 20), (-1, 9, 7),
-                                          (3, 8, 12), (2, 96, 96)])
+                                          (3, 8, 12), (5, 18, 12), (0, 7, 5), (3, 128, 128),
+                                          (2, 96, 96)])
 def test_poisson_parity(degree, n1, n2):
     vp = require_gpu()
     L1, L2 = 4 * math.pi, 3.0

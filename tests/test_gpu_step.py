@@ -163,3 +163,77 @@ def test_full_size_step_parity_sldg_f64():
     got = to_host(fd)
     assert_close(got, ref, "f64", "96^4 step")
     st.close()
+
+
+@pytest.mark.parametrize("cells,degree", [((8, 6, 8, 10), 1), ((4, 3, 4, 5), 3),
+                                          ((3, 2, 3, 4), 5)])
+def test_step_parity_other_degrees(cells, degree):
+    # two FP64 Strang steps of degree 1, 3 (the dG4 of Table 1) and 5 on
+    # non-cubic grids, against the oracle
+    vp = require_gpu()
+    w = workload("landau_8")
+    dims = tuple(c * (degree + 1) for c in cells)
+    g = strang.Grid(dims, w.lo, w.length, degree)
+    f = field.initial_condition("landau", dims, w.lo, w.length, degree, w.eps, w.k)
+    st = vp.VPState(vp.METHOD_SLDG, degree, torch.float64, dims, w.lo, w.length)
+    fd = to_dev(f)
+    tmp = torch.empty_like(fd)
+    W = torch.empty(3, dtype=torch.float64, device="cuda")
+    announce(f"strang steps degree {degree} {dims}")
+    st.step(fd, tmp, 2, w.dt, W)
+    ref, Wr = strang.run(f, g, w.dt, 2)
+    assert_close(to_host(fd), ref, "f64", f"degree {degree}")
+    assert np.max(np.abs(to_host(W) - Wr) / Wr) <= 1e-12
+    st.close()
+
+
+@pytest.mark.parametrize("name", ["landau_table1_64", "landau_table1_128"])
+def test_table1_workloads(name):
+    # dG4 at 64 and 128 dofs per direction: one full FP64 step against the
+    # oracle at 64^4; sampled lines of every sweep at 128^4
+    vp = require_gpu()
+    w = workload(name)
+    g = _grid(w, "sldg")
+    dims = w.dofs
+    st = vp.VPState(vp.METHOD_SLDG, w.degree, torch.float64, dims, w.lo, w.length)
+    if dims[0] == 64:
+        announce(f"{name}: oracle step")
+        f0 = field.initial_condition("landau", dims, w.lo, w.length, w.degree, w.eps, w.k)
+        ref = strang.step(f0, g, w.dt)
+        fd = to_dev(f0)
+        tmp = torch.empty_like(fd)
+        announce(f"{name}: device step")
+        st.step(fd, tmp, 1, w.dt)
+        assert_close(to_host(fd), ref, "f64", "64^4 dG4 step")
+    else:
+        announce(f"{name}: host input")
+        f = random_field(dims, seed=64, positive=True)
+        fin = to_dev(f)
+        out = torch.empty_like(fin)
+        rng = np.random.default_rng(65)
+        for axis in range(4):
+            if axis < 2:
+                sig = rng.uniform(-1.6, 1.6, size=dims[axis + 2])
+                sst = [0, 0, 0, 0]
+                sst[axis + 2] = 1
+            else:
+                sig = rng.uniform(-0.9, 0.9, size=dims[0] * dims[1])
+                sst = [dims[1], 1, 0, 0]
+            announce(f"{name}: sldg axis={axis}")
+            vp.sldg_advect(axis, w.degree, fin, out, to_dev(sig), shift_stride=sst)
+            got = to_host(out)
+            for ix in _sample_lines(axis, dims, 32, seed=axis + 10):
+                off = sum(ix[d] * sst[d] for d in range(4) if d != axis)
+                ref = sldg.shift_lines(f[ix][None, :], sig[off], w.degree)[0]
+                assert_close(got[ix], ref, "f64", f"axis {axis} line {ix}")
+            # spline on the same grid
+            announce(f"{name}: spline axis={axis}")
+            vp.spline_advect(axis, fin, out, to_dev(sig), shift_stride=sst)
+            got = to_host(out)
+            for ix in _sample_lines(axis, dims, 32, seed=axis + 20):
+                off = sum(ix[d] * sst[d] for d in range(4) if d != axis)
+                ref = spline.shift_lines(f[ix][None, :], sig[off])[0]
+                assert_close(got[ix], ref, "f64", f"spline axis {axis} line {ix}")
+        del fin, out
+    st.close()
+    torch.cuda.empty_cache()

@@ -7,7 +7,8 @@ the time step and the number of Strang steps.
 
 * Landau damping follows Sec. 4 (Eq. (6)): f0 = (2 pi)^-1 exp(-|v|^2/2)
   (1 + eps (cos k x1 + cos k x2)), eps = 1/2, k = 1/2, x in [0, 4 pi)^2,
-  v in [-6, 6)^2.
+  v in [-6, 6)^2.  The Table 1 workloads use it with degree 3 (dG4) at 64
+  and 128 dofs per direction.
 * Two-stream follows Sec. 5 (Eq. (7)) with the perturbation written as a sum
   (1 + eps (cos k x1 + cos k x2)) and the velocity box widened to [-9, 9)^2;
   the product form cos k x1 cos k x2 of Eq. (7) is available as ``form``.
@@ -65,6 +66,14 @@ CONFIGS = {
                                  cells=(32, 32, 32, 32), degree=2, dtype="f32",
                                  dt=0.05, steps=40, **_LANDAU,
                                  notes="differentiated run"),
+    # the comparison workload of Table 1: dG4 (degree 3), 64 and 128 dofs per
+    # direction, the spline on the same grid, tau = 0.1 as in Sec. 4
+    "landau_table1_64": Workload(name="landau_table1_64", cells=(16, 16, 16, 16),
+                                 degree=3, dtype="f64", dt=0.1, steps=20, **_LANDAU,
+                                 notes="64^4 dofs, degree 3"),
+    "landau_table1_128": Workload(name="landau_table1_128", cells=(32, 32, 32, 32),
+                                  degree=3, dtype="f64", dt=0.1, steps=20, **_LANDAU,
+                                  notes="128^4 dofs, degree 3"),
     "two_stream_96": Workload(name="two_stream_96", cells=(96, 96, 96, 96),
                               degree=2, dtype="f32", dt=0.1, steps=100,
                               **_TWO_STREAM, notes="288^4 dofs"),
