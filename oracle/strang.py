@@ -11,6 +11,12 @@ Shifts, in cells (SLDG) or grid points (spline):
   x_d sweep:  sigma = (tau/2) v_d / h_{x_d}, one value per v_d node;
   v_d sweep:  sigma = tau E_d(x1, x2) / h_{v_d}, one value per (x1, x2).
 Sweep order: x1, x2, (rho -> E), v1, v2, x1, x2.
+
+``run_merged`` takes the same steps but joins the closing x half-steps of one
+step and the opening x half-steps of the next into x sweeps of the whole step
+tau (the exact free-streaming flows compose: exp(tau/2 A) exp(tau/2 A) =
+exp(tau A)); the state f^m itself is only formed, and its diagnostics taken,
+every ``every`` steps.  With every = 1 it is ``run``.
 """
 
 from dataclasses import dataclass
@@ -81,6 +87,36 @@ def run(f0, grid, tau, nsteps, with_moments=False):
     mom = [field.moments(f, grid.degree, grid.lo, grid.length)]
     for _ in range(nsteps):
         f = step(f, grid, tau)
+        W.append(electric_field(f, grid)[2])
+        if with_moments:
+            mom.append(field.moments(f, grid.degree, grid.lo, grid.length))
+    if with_moments:
+        return f, np.array(W), np.array(mom)
+    return f, np.array(W)
+
+
+def run_merged(f0, grid, tau, nsteps, every, with_moments=False):
+    """``nsteps`` Strang steps in segments of ``every`` steps, each segment
+    x(tau/2) [field, v1, v2, x(tau)] ... [field, v1, v2, x(tau/2)].
+
+    Returns (f, W) with W[j] the electric energy of f^{j*every}, and, when
+    ``with_moments``, the moments of the same states.
+    """
+    if every < 1 or nsteps % every:
+        raise ValueError("nsteps must be a multiple of every >= 1")
+    f = np.asarray(f0, dtype=np.float64)
+    W = [electric_field(f, grid)[2]]
+    mom = [field.moments(f, grid.degree, grid.lo, grid.length)]
+    for _ in range(nsteps // every):
+        f = advect(f, 0, x_shift(grid, 0, 0.5 * tau), grid)
+        f = advect(f, 1, x_shift(grid, 1, 0.5 * tau), grid)
+        for j in range(every):
+            e1, e2, _ = electric_field(f, grid)
+            f = advect(f, 2, (tau * e1 / grid.h(2))[:, :, None, None], grid)
+            f = advect(f, 3, (tau * e2 / grid.h(3))[:, :, None, None], grid)
+            part = tau if j < every - 1 else 0.5 * tau
+            f = advect(f, 0, x_shift(grid, 0, part), grid)
+            f = advect(f, 1, x_shift(grid, 1, part), grid)
         W.append(electric_field(f, grid)[2])
         if with_moments:
             mom.append(field.moments(f, grid.degree, grid.lo, grid.length))

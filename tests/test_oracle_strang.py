@@ -84,6 +84,58 @@ def test_step_is_deterministic_and_restartable():
     assert np.array_equal(a, b)
 
 
+def test_merged_run_with_every_one_is_the_plain_run():
+    w = workload("landau_8")
+    g = strang.Grid(w.dofs, w.lo, w.length, w.degree)
+    f0 = field.initial_condition("landau", w.dofs, w.lo, w.length, w.degree, w.eps, w.k)
+    a, Wa = strang.run(f0, g, w.dt, 3)
+    b, Wb = strang.run_merged(f0, g, w.dt, 3, 1)
+    assert np.array_equal(a, b) and np.array_equal(Wa, Wb)
+
+
+@pytest.mark.parametrize("degree", [0, None])
+def test_merged_run_equals_plain_run_for_whole_cell_x_shifts(degree):
+    # tau = 4 h_x and velocity nodes at half-integers: every x half-step
+    # shifts by an odd whole number of cells, so x(tau/2) x(tau/2) = x(tau)
+    # exactly (permutations) and merging changes nothing but round-off;
+    # a wrong merged shift, a missing closing half-step or a field taken at
+    # the wrong state would not
+    dims = (8, 8, 12, 12)
+    lo = (0.0, 0.0, -6.0, -6.0)
+    ln = (8.0, 8.0, 12.0, 12.0)
+    g = strang.Grid(dims, lo, ln, degree)
+    tau = 4.0 * g.h(0)
+    assert np.allclose(strang.x_shift(g, 0, 0.5 * tau) % 1.0, 0.0)
+    f0 = field.initial_condition("landau", dims, lo, ln, degree, 0.3, 2 * math.pi / 8.0)
+    a, Wa = strang.run(f0, g, tau, 4)
+    b, Wb = strang.run_merged(f0, g, tau, 4, 4)
+    tol = 0.0 if degree == 0 else 1e-13
+    assert np.max(np.abs(a - b)) <= tol * np.max(np.abs(a))
+    assert abs(Wa[-1] - Wb[-1]) <= max(tol, 1e-15) * Wa[-1] * 10
+    assert len(Wb) == 2 and Wb[0] == Wa[0]
+
+
+def test_merged_run_converges_to_the_plain_run():
+    # the two schemes differ only by how often the x flows are projected
+    # (x(tau/2) twice against x(tau) once): with the perturbation along x1
+    # only, the difference after a fixed time shrinks as x1 and v1 are refined
+    diffs = []
+    for nc in (8, 16):
+        dims = (3 * nc, 3, 3 * nc, 3)
+        lo = (0.0, 0.0, -6.0, -6.0)
+        ln = (4 * math.pi, 4 * math.pi, 12.0, 12.0)
+        g = strang.Grid(dims, lo, ln, 2)
+        x1, v1, v2 = g.nodes(0), g.nodes(2), g.nodes(3)
+        f0 = ((1 + 0.2 * np.cos(0.5 * x1))[:, None, None, None]
+              * np.exp(-0.5 * v1 ** 2)[None, None, :, None]
+              * np.exp(-0.5 * v2 ** 2)[None, None, None, :]
+              * np.ones((1, dims[1], 1, 1)) / (2 * math.pi))
+        a, _ = strang.run(f0, g, 0.2, 4)
+        b, _ = strang.run_merged(f0, g, 0.2, 4, 4)
+        diffs.append(np.max(np.abs(a - b)) / np.max(np.abs(a)))
+    assert 0 < diffs[1] < diffs[0] / 2.5 and diffs[0] < 1e-3, diffs
+
+
 def _golden():
     import json
     import os
