@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the timing of the adjoint step and its kernels")
     ap.add_argument("--adjoint-steps", type=int, default=20)
+    ap.add_argument("--no-merged", action="store_true",
+                    help="skip the timing of runs with merged x half-steps")
+    ap.add_argument("--diag-every", type=int, default=10)
     ap.add_argument("--copy-ref", type=int, default=0,
                     help="plain device copies of one f buffer before the run (a "
                          "reference kernel of known size for hardware counters)")
@@ -173,6 +176,36 @@ def _event_ms(torch, stream, fn, reps):
     b.record(stream)
     b.synchronize()
     return a.elapsed_time(b) / reps
+
+
+def run_merged(vp, torch, w, dt, methods, steps, every, stream):
+    """The same steps with the x half-steps merged between states formed
+    every `every` steps (4 + 2/every sweeps per step instead of 6)."""
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    steps = max(every, steps // every * every)
+    out = {"diag_every": every, "steps": steps, "sweeps_per_step": 4 + 2.0 / every}
+    for m in methods:
+        method = vp.METHOD_SLDG if m == "sldg" else vp.METHOD_SPLINE
+        deg = w.degree if m == "sldg" else -1
+        st = vp.VPState(method, w.degree, tdt, w.dofs, w.lo, w.length)
+        f = torch.empty(w.dofs, dtype=tdt, device="cuda")
+        tmp = torch.empty_like(f)
+        vp.vp_init(vp.IC_LANDAU if w.ic == "landau" else vp.IC_TWO_STREAM_SUM,
+                   w.eps, w.k, w.v0, deg, f, w.lo, w.length)
+        W = torch.empty(steps // every + 1, dtype=torch.float64, device="cuda")
+        mom = torch.empty(4 * (steps // every + 1), dtype=torch.float64, device="cuda")
+        st.run(f, tmp, every, w.dt, every, None, None, stream)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        st.run(f, tmp, steps, w.dt, every, W, mom, stream)
+        b.record(stream)
+        b.synchronize()
+        out[m] = {"ms_per_step": a.elapsed_time(b) / steps,
+                  "W_el_last": float(W[-1].item())}
+        st.close()
+        del f, tmp
+    return out
 
 
 def step_shifts(w, degree):
@@ -342,6 +375,12 @@ def main():
         "W_el_last": W_last,
         "rel_mass_drift": mass_drift,
     }
+
+    if not a.no_merged:
+        mr = run_merged(vp, torch, w, dt, methods, a.steps, a.diag_every, stream)
+        for r in runs:
+            mr[r["name"]]["speedup_vs_every_step"] = r["ms_per_step"] / mr[r["name"]]["ms_per_step"]
+        out["merged_run"] = mr
 
     if w.name.startswith("landau_table1_"):
         # the paper's Table 1 (whole Strang steps, FP64 assumed, 16 threads

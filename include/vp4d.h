@@ -197,6 +197,26 @@ VP4D_API vp_status vp_strang_step(vp_state* st, void* f, void* f_tmp, int nsteps
                          double tau, double* W_trace, double* moments,
                          void* stream);
 
+/*
+ * vp_strang_run -- the same `nsteps` Strang steps with the state formed only
+ * every `diag_every` steps.  Inside a segment of diag_every steps the closing
+ * x half-steps of one step and the opening ones of the next are one x sweep
+ * of the whole step (the exact free-streaming flows compose, Sec. 2:
+ * exp(tau/2 A) exp(tau/2 A) = exp(tau A)), so a segment of k steps takes
+ * 4k + 2 sweeps instead of 6k; the discrete result differs from
+ * vp_strang_step (one projection instead of two per x flow) except for
+ * diag_every = 1, where the two are identical.
+ *
+ *   nsteps     a multiple of diag_every >= 1 (else VP_ERR_ARG).
+ *   W_trace    device, nsteps/diag_every + 1 doubles or NULL: W of f^0,
+ *              f^{diag_every}, ..., f^{nsteps} (relative to the entry state).
+ *   moments    device, 4*(nsteps/diag_every + 1) doubles or NULL.
+ * Other arguments as for vp_strang_step.
+ */
+VP4D_API vp_status vp_strang_run(vp_state* st, void* f, void* f_tmp, int nsteps,
+                        double tau, int diag_every, double* W_trace,
+                        double* moments, void* stream);
+
 /* ------------------------------------------------------------------------
  * Reverse mode.  Transposes are taken with respect to the Euclidean inner
  * product of the dof arrays, <a, b> = sum_i a_i b_i (the discrete map is

@@ -278,6 +278,20 @@ class VPState:
             None if moments is None else _f64(moments, "moments", 4 * (nsteps + 1)),
             _stream(stream)))
 
+    def run(self, f, f_tmp, nsteps, tau, diag_every, W_trace=None, moments=None, stream=None):
+        """``nsteps`` Strang steps with merged x half-steps between the states
+        f^0, f^{diag_every}, ... (``vp_strang_run``)."""
+        for t, n in ((f, "f"), (f_tmp, "f_tmp")):
+            if tuple(t.shape) != self.dims or t.dtype != self.dtype:
+                raise ValueError(f"{n} must be {self.dtype} of shape {self.dims}")
+        nd = nsteps // diag_every + 1 if diag_every > 0 else 1
+        _check("vp_strang_run", lib().vp_strang_run(
+            self._h, _dev(f, "f"), _dev(f_tmp, "f_tmp"), int(nsteps), float(tau),
+            int(diag_every),
+            None if W_trace is None else _f64(W_trace, "W_trace", nd),
+            None if moments is None else _f64(moments, "moments", 4 * nd),
+            _stream(stream)))
+
     def _check_f(self, t, name):
         if tuple(t.shape) != self.dims or t.dtype != self.dtype:
             raise ValueError(f"{name} must be {self.dtype} of shape {self.dims}")

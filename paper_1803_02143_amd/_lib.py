@@ -53,6 +53,8 @@ SIGNATURES = {
     "vp_destroy": (None, [_vp]),
     "vp_strang_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double,
                                       _dp, _dp, _vp]),
+    "vp_strang_run": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_int, _dp, _dp, _vp]),
     "sldg_advect_adjoint": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64x4,
                                            _vp, _vp, _dp, _i64x4, _vp]),
     "sldg_advect_dshift": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64x4,

@@ -283,24 +283,28 @@ template <typename T, int AXIS, int MODE>
 __global__ void __launch_bounds__(kBlock)
 spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ lam,
            double* __restrict__ g, const double* __restrict__ shift, ShiftMap sm,
-           int64_t inner, int L, int64_t tiles_per_outer, SplineParams<T> sp) {
+           int64_t nlines, int64_t inner, int L, SplineParams<T> sp) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[MODE == kDshift ? kBlock : 1];
     const int n = sp.n;
     T* buf = reinterpret_cast<T*>(smem);   // [n][L]
 
-    const int64_t o = blockIdx.x / tiles_per_outer;
-    const int64_t k0 = (blockIdx.x - o * tiles_per_outer) * L;
-    const int nl = static_cast<int>(min(static_cast<int64_t>(L), inner - k0));
-    const int64_t base = o * n * inner + k0;
+    // the tile holds lines line0 .. line0+nl-1 of the flattened (outer,
+    // inner) line index; a tile may straddle two outer indices
+    const int64_t line0 = static_cast<int64_t>(blockIdx.x) * L;
+    const int nl = static_cast<int>(min(static_cast<int64_t>(L), nlines - line0));
 
     const int l = threadIdx.x % L;
+    const int64_t line = line0 + min(l, nl - 1);
+    const int64_t o = line / inner;
+    const int64_t kl = line - o * inner;
+    const int64_t lbase = o * n * inner + kl;       // element 0 of the thread's line
     const int Q = kBlock / L;
     const int S = (n + Q - 1) / Q;
     const int b = min(n, (static_cast<int>(threadIdx.x) / L) * S);
     const int e = min(n, b + S);
     const bool active = l < nl && b < e;
-    const T* __restrict__ src = fin + base + l;
+    const T* __restrict__ src = fin + lbase;
     if (active) {
         // batches of kU independent loads keep many requests in flight
         int i = b;
@@ -318,7 +322,7 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     constexpr int SM = SegMax<T>::value;
     T lv[MODE == kDshift ? SM : 1];
     if (MODE == kDshift && active) {
-        const T* __restrict__ lm = lam + base + l;
+        const T* __restrict__ lm = lam + lbase;
 #pragma unroll
         for (int t = 0; t < SM; ++t)
             lv[t] = lm[static_cast<int64_t>(min(b + t, e - 1)) * inner];
@@ -327,7 +331,7 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     T w0 = T(0), w1 = T(0), w2 = T(0), w3 = T(0);
     if (active) {
         T wq[4];
-        const double sigma = shift[shift_offset(sm, o, k0 + l)];
+        const double sigma = shift[shift_offset(sm, o, kl)];
         if (MODE == kDshift)
             spline_dweights<T>(sigma, n, s, wq);
         else
@@ -342,7 +346,7 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     spline_solve_segment<T>(buf + l, L, b, e, active, sp);
     if (MODE == kAdj) {
         if (active) {
-            T* __restrict__ dst = fout + base + l;
+            T* __restrict__ dst = fout + lbase;
             for (int i = b; i < e; ++i) dst[static_cast<int64_t>(i) * inner] = buf[i * L + l];
         }
         return;
@@ -350,7 +354,7 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     double acc = 0.0;
     if (active) {
         // sliding window over omega_{i-s-2 .. i-s+1}
-        T* __restrict__ dst = fout + base + l;
+        T* __restrict__ dst = fout + lbase;
         int j = first_tap(b, s, n);
         T c0 = buf[j * L + l];
         j = next_idx(j, n);
@@ -408,7 +412,7 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         if (threadIdx.x < nl) {
             double t = 0.0;
             for (int q = 0; q < Q; ++q) t += red[q * L + threadIdx.x];
-            g[o * inner + k0 + threadIdx.x] = t;
+            g[line0 + threadIdx.x] = t;
         }
     }
 }
@@ -571,31 +575,28 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
     T* out = static_cast<T*>(fout);
     const T* lm = static_cast<const T*>(lam);
     if (axis < 3) {
-        // lines per tile: a power of two dividing the fastest block when one
-        // of at least 16 does, within the LDS budget
+        // lines per tile: a power of two up to 64 within the LDS budget; tiles
+        // run over the flattened line index
         int L = 64;
-        while (L > 16 && inner % L) L /= 2;
-        if (inner % L) L = 64;
-        while (L > 1 && (static_cast<size_t>(n) * L * sizeof(T) > kTileBytes || L / 2 >= inner))
-            L /= 2;
+        while (L > 1 && static_cast<size_t>(n) * L * sizeof(T) > kTileBytes) L /= 2;
         const size_t lds = static_cast<size_t>(n) * L * sizeof(T);
         if (lds > kTileBytes)
             return set_error(VP_ERR_UNSUPPORTED,
                              "spline_advect: line of %d points too long for the LDS tile", n);
-        const int64_t tiles = (inner + L - 1) / L;
-        const int64_t grid64 = outer * tiles;
+        const int64_t nlines = outer * inner;
+        const int64_t grid64 = (nlines + L - 1) / L;
         if (grid64 >= (int64_t(1) << 31))
             return set_error(VP_ERR_UNSUPPORTED, "spline_advect: grid too large");
         const unsigned grid = static_cast<unsigned>(grid64);
         switch (axis) {
             case 0:
-                spline_col<T, 0, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, inner, L, tiles, sp);
+                spline_col<T, 0, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp);
                 break;
             case 1:
-                spline_col<T, 1, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, inner, L, tiles, sp);
+                spline_col<T, 1, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp);
                 break;
             default:
-                spline_col<T, 2, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, inner, L, tiles, sp);
+                spline_col<T, 2, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp);
                 break;
         }
         return check_launch("spline_col");

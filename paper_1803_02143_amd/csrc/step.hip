@@ -25,6 +25,7 @@ struct vp_state {
     double h[4];  // shift unit per axis: cell width or grid spacing
     double* buf;  // one device allocation holding every 2D array below
     double *rho, *e1, *e2, *sig_v1, *sig_v2, *sig_x1, *sig_x2, *vnode1, *vnode2;
+    double *sig_x1f, *sig_x2f;  // x shifts of a whole step (merged half-steps)
     double* partial;  // 4 * n1 * n2
     double *gs1, *gs2, *rho_bar;  // adjoint: shift gradients and transposed density
     void* pws;        // Poisson workspace
@@ -172,7 +173,7 @@ extern "C" vp_status vp_create(vp_state** out, int method, int degree, vp_dtype 
     const int64_t nx = dims[0] * dims[1];
     const size_t pws = vp_poisson_workspace(deg, dims[0], dims[1]);
     const size_t ndbl = static_cast<size_t>(nx) * (5 + 4 + 3) +
-                        2 * static_cast<size_t>(dims[2] + dims[3]) + pws / sizeof(double) + 64;
+                        3 * static_cast<size_t>(dims[2] + dims[3]) + pws / sizeof(double) + 64;
     void* mem = nullptr;
     hipError_t e = hipMalloc(&mem, ndbl * sizeof(double));
     if (e != hipSuccess) {
@@ -195,6 +196,8 @@ extern "C" vp_status vp_create(vp_state** out, int method, int degree, vp_dtype 
     st->sig_x2 = p; p += dims[3];
     st->vnode1 = p; p += dims[2];
     st->vnode2 = p; p += dims[3];
+    st->sig_x1f = p; p += dims[2];
+    st->sig_x2f = p; p += dims[3];
     p = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(p) + 255) & ~uintptr_t(255));
     st->pws = p;
     // velocity node coordinates, used for the x-sweep shifts
@@ -232,61 +235,103 @@ extern "C" void vp_destroy(vp_state* st) {
     delete st;
 }
 
-extern "C" vp_status vp_strang_step(vp_state* st, void* f, void* f_tmp, int nsteps,
-                                    double tau, double* W_trace, double* moments,
-                                    void* stream) {
-    clear_error();
-    if (!st || !f || !f_tmp) return set_error(VP_ERR_ARG, "NULL pointer argument");
-    if (nsteps < 0) return set_error(VP_ERR_ARG, "nsteps %d < 0", nsteps);
-    if (!(tau == tau) || tau > 1e300 || tau < -1e300) return set_error(VP_ERR_ARG, "tau not finite");
-    const size_t bytes = static_cast<size_t>(st->dims[0] * st->dims[1] * st->dims[2] *
-                                             st->dims[3]) * dtype_size(st->dt);
-    if (ranges_overlap(f, f_tmp, bytes)) return set_error(VP_ERR_ALIAS, "f and f_tmp overlap");
-    int cur = -1;
-    VP_HIP_TRY(hipGetDevice(&cur));
-    if (cur != st->device)
-        return set_error(VP_ERR_ARG, "state belongs to device %d, current device is %d",
-                         st->device, cur);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    vp_status rc = VP_OK;
+namespace vp {
+namespace {
 
-    // x-sweep shifts: (tau/2) v / h_x, one value per velocity node
+// nsteps Strang steps in segments of `every` steps.  A segment opens with the
+// x half-steps, joins the closing x half-steps of each step with the opening
+// ones of the next into whole-step x sweeps, and closes with the x
+// half-steps; the diagnostics of the state after each segment go to
+// W_trace[j] / moments[4 j].  With every = 1 this is the plain Strang step.
+// Every segment has an even number of sweeps, so the result is back in f.
+vp_status strang_run(vp_state* st, void* f, void* f_tmp, int nsteps, double tau, int every,
+                     double* W_trace, double* moments, hipStream_t s) {
+    vp_status rc = VP_OK;
     const int64_t nv = st->dims[2] > st->dims[3] ? st->dims[2] : st->dims[3];
+    // x-sweep shifts (tau/2) v / h_x and tau v / h_x, one value per velocity node
     xshift<<<blocks_for(nv, 256), 256, 0, s>>>(st->vnode1, st->vnode2, st->dims[2],
                                                st->dims[3], 0.5 * tau / st->h[0],
                                                0.5 * tau / st->h[1], st->sig_x1,
                                                st->sig_x2);
     if ((rc = check_launch("xshift")) != VP_OK) return rc;
-
-    if (W_trace || moments) {
-        rc = diagnostics(st, f, W_trace, moments, s);
-        if (rc != VP_OK) return rc;
+    if (every > 1) {
+        xshift<<<blocks_for(nv, 256), 256, 0, s>>>(st->vnode1, st->vnode2, st->dims[2],
+                                                   st->dims[3], tau / st->h[0], tau / st->h[1],
+                                                   st->sig_x1f, st->sig_x2f);
+        if ((rc = check_launch("xshift")) != VP_OK) return rc;
     }
-    for (int m = 0; m < nsteps; ++m) {
+    const bool diag = W_trace || moments;
+    if (diag && (rc = diagnostics(st, f, W_trace, moments, s)) != VP_OK) return rc;
+    for (int seg = 0; seg < nsteps / every; ++seg) {
         if ((rc = sweep(st, 0, f, f_tmp, st->sig_x1, s)) != VP_OK) return rc;
         if ((rc = sweep(st, 1, f_tmp, f, st->sig_x2, s)) != VP_OK) return rc;
-        mark(st, VP_TIMER_FIELD, s);
-        rc = density_impl(st->degree, st->dt, st->dims, f, st->len[2], st->len[3],
-                          st->rho, s);
-        // E of the half-step state and the v-sweep shifts tau E_d / h_{v_d}
-        if (rc == VP_OK)
-            rc = poisson_impl_shift(st->degree, st->dims[0], st->dims[1], st->len[0],
-                                    st->len[1], st->rho, st->e1, st->e2, nullptr, st->pws,
-                                    st->sig_v1, st->sig_v2, tau / st->h[2],
-                                    tau / st->h[3], s);
-        if (rc != VP_OK) return rc;
-        mark(st, VP_TIMER_FIELD, s);
-        if ((rc = sweep(st, 2, f, f_tmp, st->sig_v1, s)) != VP_OK) return rc;
-        if ((rc = sweep(st, 3, f_tmp, f, st->sig_v2, s)) != VP_OK) return rc;
-        if ((rc = sweep(st, 0, f, f_tmp, st->sig_x1, s)) != VP_OK) return rc;
-        if ((rc = sweep(st, 1, f_tmp, f, st->sig_x2, s)) != VP_OK) return rc;
-        if (W_trace || moments) {
-            rc = diagnostics(st, f, W_trace ? W_trace + m + 1 : nullptr,
-                             moments ? moments + 4 * (m + 1) : nullptr, s);
+        for (int j = 0; j < every; ++j) {
+            mark(st, VP_TIMER_FIELD, s);
+            rc = density_impl(st->degree, st->dt, st->dims, f, st->len[2], st->len[3],
+                              st->rho, s);
+            // E of the current state and the v-sweep shifts tau E_d / h_{v_d}
+            if (rc == VP_OK)
+                rc = poisson_impl_shift(st->degree, st->dims[0], st->dims[1], st->len[0],
+                                        st->len[1], st->rho, st->e1, st->e2, nullptr,
+                                        st->pws, st->sig_v1, st->sig_v2, tau / st->h[2],
+                                        tau / st->h[3], s);
+            if (rc != VP_OK) return rc;
+            mark(st, VP_TIMER_FIELD, s);
+            if ((rc = sweep(st, 2, f, f_tmp, st->sig_v1, s)) != VP_OK) return rc;
+            if ((rc = sweep(st, 3, f_tmp, f, st->sig_v2, s)) != VP_OK) return rc;
+            const bool last = j == every - 1;
+            if ((rc = sweep(st, 0, f, f_tmp, last ? st->sig_x1 : st->sig_x1f, s)) != VP_OK)
+                return rc;
+            if ((rc = sweep(st, 1, f_tmp, f, last ? st->sig_x2 : st->sig_x2f, s)) != VP_OK)
+                return rc;
+        }
+        if (diag) {
+            rc = diagnostics(st, f, W_trace ? W_trace + seg + 1 : nullptr,
+                             moments ? moments + 4 * (seg + 1) : nullptr, s);
             if (rc != VP_OK) return rc;
         }
     }
     return VP_OK;
+}
+
+vp_status check_run_args(vp_state* st, void* f, void* f_tmp, int nsteps, double tau) {
+    if (!st || !f || !f_tmp) return set_error(VP_ERR_ARG, "NULL pointer argument");
+    if (nsteps < 0) return set_error(VP_ERR_ARG, "nsteps %d < 0", nsteps);
+    if (!(tau == tau) || tau > 1e300 || tau < -1e300) return set_error(VP_ERR_ARG, "tau not finite");
+    if (ranges_overlap(f, f_tmp, f_bytes(st))) return set_error(VP_ERR_ALIAS, "f and f_tmp overlap");
+    int cur = -1;
+    VP_HIP_TRY(hipGetDevice(&cur));
+    if (cur != st->device)
+        return set_error(VP_ERR_ARG, "state belongs to device %d, current device is %d",
+                         st->device, cur);
+    return VP_OK;
+}
+
+}  // namespace
+}  // namespace vp
+
+extern "C" vp_status vp_strang_step(vp_state* st, void* f, void* f_tmp, int nsteps,
+                                    double tau, double* W_trace, double* moments,
+                                    void* stream) {
+    clear_error();
+    vp_status rc = check_run_args(st, f, f_tmp, nsteps, tau);
+    if (rc != VP_OK) return rc;
+    return strang_run(st, f, f_tmp, nsteps, tau, 1, W_trace, moments,
+                      static_cast<hipStream_t>(stream));
+}
+
+extern "C" vp_status vp_strang_run(vp_state* st, void* f, void* f_tmp, int nsteps, double tau,
+                                   int diag_every, double* W_trace, double* moments,
+                                   void* stream) {
+    clear_error();
+    vp_status rc = check_run_args(st, f, f_tmp, nsteps, tau);
+    if (rc != VP_OK) return rc;
+    if (diag_every < 1) return set_error(VP_ERR_ARG, "diag_every %d < 1", diag_every);
+    if (nsteps % diag_every)
+        return set_error(VP_ERR_ARG, "nsteps %d is not a multiple of diag_every %d", nsteps,
+                         diag_every);
+    return strang_run(st, f, f_tmp, nsteps, tau, diag_every, W_trace, moments,
+                      static_cast<hipStream_t>(stream));
 }
 
 extern "C" vp_status vp_timing_enable(vp_state* st, int enable) {

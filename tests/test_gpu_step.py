@@ -237,3 +237,49 @@ def test_table1_workloads(name):
         del fin, out
     st.close()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("method", ["sldg", "spline"])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_merged_run_parity(method, dt):
+    # 10 steps with the x half-steps merged inside segments of 5 steps: the
+    # two formed states, their W and moments against the oracle's merged run
+    vp = require_gpu()
+    w = workload("landau_8")
+    g = _grid(w, method)
+    f0 = field.initial_condition("landau", w.dofs, w.lo, w.length, g.degree, w.eps, w.k)
+    st = vp.VPState(vp.METHOD_SLDG if method == "sldg" else vp.METHOD_SPLINE,
+                    w.degree, torch.float64 if dt == "f64" else torch.float32,
+                    w.dofs, w.lo, w.length)
+    fd = to_dev(f0, dt)
+    f_in = to_host(fd)
+    tmp = torch.empty_like(fd)
+    W = torch.empty(3, dtype=torch.float64, device="cuda")
+    mom = torch.empty(12, dtype=torch.float64, device="cuda")
+    announce(f"merged run {method} {dt}")
+    st.run(fd, tmp, 10, w.dt, 5, W, mom)
+    ref, Wr, mr = strang.run_merged(f_in, g, w.dt, 10, 5, with_moments=True)
+    assert_close(to_host(fd), ref, dt, "merged run state")
+    tol = 1e-12 if dt == "f64" else 1e-5
+    assert np.max(np.abs(to_host(W) - Wr) / Wr) <= tol
+    np.testing.assert_allclose(to_host(mom).reshape(3, 4), mr, rtol=tol)
+    st.close()
+
+
+def test_run_with_every_step_formed_is_the_plain_step():
+    vp = require_gpu()
+    w = workload("landau_8")
+    st = vp.VPState(vp.METHOD_SLDG, w.degree, torch.float64, w.dofs, w.lo, w.length)
+    a = torch.empty(w.dofs, dtype=torch.float64, device="cuda")
+    vp.vp_init(vp.IC_LANDAU, w.eps, w.k, 0.0, w.degree, a, w.lo, w.length)
+    b = a.clone()
+    tmp = torch.empty_like(a)
+    Wa = torch.empty(5, dtype=torch.float64, device="cuda")
+    Wb = torch.empty(5, dtype=torch.float64, device="cuda")
+    announce("run every=1 against step")
+    st.step(a, tmp, 4, w.dt, Wa)
+    st.run(b, tmp, 4, w.dt, 1, Wb)
+    assert torch.equal(a, b) and torch.equal(Wa, Wb)
+    with pytest.raises(vp.VPError):
+        st.run(b, tmp, 5, w.dt, 2)
+    st.close()
