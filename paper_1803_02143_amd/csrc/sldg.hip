@@ -235,7 +235,7 @@ sldg_col(const T* __restrict__ fin, T* __restrict__ fout,
     // output cell fed by input cells (c-1, c): c+s, or c-1-s for the transpose
     int i = ADJ ? nc - 1 - s : s;
     // chunks of CU cells: all their loads are issued before the first use
-    constexpr int CU = M <= 3 ? 4 : 2;
+    constexpr int CU = (M <= 3 ? 4 : 2) * (sizeof(T) == 4 ? 2 : 1);
     int c = 0;
     for (; c + CU <= nc - 1; c += CU) {
         T cur[CU][M];

@@ -417,10 +417,10 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     }
 }
 
-// Lines along the contiguous axis.  Loads and stores go row by row, one
-// wavefront per row (consecutive lanes, consecutive addresses; the row's
-// weights and shift are wavefront-uniform); the solve gives thread t row
-// r = t % R and segment q = t / R.  Modes as for spline_col.
+// Lines along the contiguous axis.  The R rows of a tile are one contiguous
+// range of memory: loads and stores run over it flat (consecutive lanes,
+// consecutive addresses, no idle lanes at row ends); the solve gives thread t
+// row r = t % R and segment q = t / R.  Modes as for spline_col.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kBlock)
 spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ lam,
@@ -438,24 +438,34 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     constexpr int kWaves = kBlock / 64;
-    // rows r = wave, wave + 4, ...; clamped indices instead of branches, so
-    // that the kU loads of a batch issue back to back; only the LDS stores
-    // are guarded
-    for (int r0 = wave; r0 < nr; r0 += kWaves * kU) {
-        for (int i0 = 0; i0 < n; i0 += 64) {
-            const int i = i0 + lane;
-            const int ic = i < n ? i : n - 1;
+    // the tile's rows are contiguous in memory: flat element e = r*n + i,
+    // (r, i) advanced by kBlock elements per round; kU loads in flight with
+    // clamped indices, only the LDS stores guarded
+    const int cnt = nr * n;
+    const int dr = kBlock / n;
+    const int di = kBlock - dr * n;
+    {
+        const T* __restrict__ src = fin + row0 * n;
+        int r = static_cast<int>(threadIdx.x) / n;
+        int i = static_cast<int>(threadIdx.x) - r * n;
+        for (int e0 = threadIdx.x; e0 < cnt; e0 += kU * kBlock) {
             T v[kU];
+            int pos[kU];
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                const int r = r0 + u * kWaves;
-                v[u] = fin[(row0 + (r < nr ? r : nr - 1)) * n + ic];
+                const int e = e0 + u * kBlock;
+                v[u] = src[e < cnt ? e : cnt - 1];
+                pos[u] = r * ld + i;
+                r += dr;
+                i += di;
+                if (i >= n) {
+                    i -= n;
+                    ++r;
+                }
             }
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int r = r0 + u * kWaves;
-                if (r < nr && i < n) buf[r * ld + i] = v[u];
-            }
+            for (int u = 0; u < kU; ++u)
+                if (e0 + u * kBlock < cnt) buf[pos[u]] = v[u];
         }
     }
     if (threadIdx.x < nr) {
@@ -488,23 +498,50 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                                active);
         spline_solve_segment<T>(buf + r * ld, 1, b, e, active, sp);
     }
-    for (int r = wave; MODE != kDshift && r < nr; r += kWaves) {
-        const T* row = buf + r * ld;
-        T* __restrict__ dst = fout + (row0 + r) * n;
-        if (MODE == kAdj) {
-            for (int i = lane; i < n; i += 64) dst[i] = row[i];
-            continue;
+    if (MODE != kDshift && sizeof(T) == 8) {
+        // FP64: row by row, the row's weights and shift held in registers
+        for (int r = wave; r < nr; r += kWaves) {
+            const T* row = buf + r * ld;
+            T* __restrict__ dst = fout + (row0 + r) * n;
+            if (MODE == kAdj) {
+                for (int i = lane; i < n; i += 64) dst[i] = row[i];
+                continue;
+            }
+            const T w0 = wts[4 * r + 0], w1 = wts[4 * r + 1];
+            const T w2 = wts[4 * r + 2], w3 = wts[4 * r + 3];
+            const int s = sh[r];
+            for (int i = lane; i < n; i += 64) {
+                const int j0 = first_tap(i, s, n);
+                const int j1 = next_idx(j0, n), j2 = next_idx(j1, n), j3 = next_idx(j2, n);
+                dst[i] = fma(w3, row[j3], fma(w2, row[j2], fma(w1, row[j1], w0 * row[j0])));
+            }
         }
-        const T w0 = wts[4 * r + 0], w1 = wts[4 * r + 1];
-        const T w2 = wts[4 * r + 2], w3 = wts[4 * r + 3];
-        const int s = sh[r];
-        for (int i = lane; i < n; i += 64) {
-            const int j0 = first_tap(i, s, n);
-            const int j1 = next_idx(j0, n), j2 = next_idx(j1, n), j3 = next_idx(j2, n);
-            dst[i] = fma(w3, row[j3], fma(w2, row[j2], fma(w1, row[j1], w0 * row[j0])));
-        }
+        return;
     }
-    if (MODE != kDshift) return;
+    if (MODE != kDshift) {
+        // FP32: flat stores in memory order (no idle lanes at row ends)
+        T* __restrict__ dst = fout + row0 * n;
+        int r = static_cast<int>(threadIdx.x) / n;
+        int i = static_cast<int>(threadIdx.x) - r * n;
+        for (int e = threadIdx.x; e < cnt; e += kBlock) {
+            const T* row = buf + r * ld;
+            if (MODE == kAdj) {
+                dst[e] = row[i];
+            } else {
+                const int j0 = first_tap(i, sh[r], n);
+                const int j1 = next_idx(j0, n), j2 = next_idx(j1, n), j3 = next_idx(j2, n);
+                const T* w = wts + 4 * r;
+                dst[e] = fma(w[3], row[j3], fma(w[2], row[j2], fma(w[1], row[j1], w[0] * row[j0])));
+            }
+            r += dr;
+            i += di;
+            if (i >= n) {
+                i -= n;
+                ++r;
+            }
+        }
+        return;
+    }
     // shift derivative: kU rows per wavefront at a time, their lam loads
     // issued back to back (clamped indices), one FP64 sum per row
     for (int r0 = wave; r0 < nr; r0 += kWaves * kU) {
