@@ -144,6 +144,78 @@ velocity_reduce(const T* __restrict__ f, int n3, int n4, AxisGrid g3,
     }
 }
 
+// The same reductions without weight tables.  Lane l reads the elements
+// e = l + 64 t of a point's block.  When 64 P is a multiple of N4 m (m nodes
+// per cell, the period of the weights), the element in slot k = t mod P of
+// every round of P loads has the same (c mod m, e mod N4): its weight
+// W3_c W4_e and v2^2 are fixed per lane and slot, and v1 grows by the same
+// step each round.  So the weights live in registers and every value costs
+// one FMA (seven with the diagnostics).
+template <typename T, bool DIAG, int P>
+__global__ void __launch_bounds__(kRedBlock)
+velocity_reduce_slots(const T* __restrict__ f, int n3, int n4, AxisGrid g3,
+                      AxisGrid g4, double* __restrict__ out, int64_t nblk) {
+    constexpr int kWaves = kRedBlock / 64;
+    const int lane = threadIdx.x & 63;
+    const int total = n3 * n4;
+    double wk[P], a1[DIAG ? P : 1], v2q[DIAG ? P : 1];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const int e = lane + 64 * k;
+        const int c = e / n4;
+        const int d = e - c * n4;
+        wk[k] = node_weight(g3, c) * node_weight(g4, d);
+        if (DIAG) {
+            a1[k] = node_coord(g3, c);
+            const double v2 = node_coord(g4, d);
+            v2q[k] = v2 * v2;
+        }
+    }
+    // rows per round of P loads, and the v1 step that goes with them
+    const int rows = 64 * P / n4;
+    const double dv1 = static_cast<double>(rows / g3.m) * g3.h;
+    for (int64_t b = static_cast<int64_t>(blockIdx.x) * kWaves + (threadIdx.x >> 6); b < nblk;
+         b += static_cast<int64_t>(gridDim.x) * kWaves) {
+        const T* __restrict__ blk = f + b * total;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        int it = 0;
+        for (int q0 = lane; q0 < total; q0 += 64 * P, ++it) {
+            T x[P];
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const int q = q0 + 64 * k;
+                x[k] = blk[q < total ? q : total - 1];
+            }
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const double xv = q0 + 64 * k < total ? static_cast<double>(x[k]) : 0.0;
+                const double xw = wk[k] * xv;
+                acc[0] += xw;
+                if (DIAG) {
+                    const double v1 = fma(static_cast<double>(it), dv1, a1[k]);
+                    acc[1] = fma(wk[k], fabs(xv), acc[1]);
+                    acc[2] = fma(xw, xv, acc[2]);
+                    acc[3] = fma(xw, fma(v1, v1, v2q[k]), acc[3]);
+                }
+            }
+        }
+        const double s0 = wave_sum64(acc[0]);
+        if (DIAG) {
+            const double s1 = wave_sum64(acc[1]);
+            const double s2 = wave_sum64(acc[2]);
+            const double s3 = wave_sum64(acc[3]);
+            if (lane == 0) {
+                out[b] = s0;
+                out[nblk + b] = s1;
+                out[2 * nblk + b] = s2;
+                out[3 * nblk + b] = s3;
+            }
+        } else if (lane == 0) {
+            out[b] = s0;
+        }
+    }
+}
+
 constexpr int kFinalBlock = 1024;
 
 // out4 = (mass, L1, L2, kinetic) from the per-(x1,x2) partial sums.
@@ -251,12 +323,30 @@ vp_status launch_reduce(bool diag, const int64_t dims[4], const void* f,
     // one wavefront per (x1, x2) point, at most 8192 workgroups
     int64_t grid = (nblk + kRedBlock / 64 - 1) / (kRedBlock / 64);
     if (grid > 8192) grid = 8192;
+    // register weights when the weight pattern repeats within a few rounds
+    const int64_t nm = static_cast<int64_t>(n4) * g3.m;
+    int64_t gg = 64;
+    for (int64_t a = nm; a; ) { const int64_t t = gg % a; gg = a; a = t; }
+    const int64_t period = nm / gg;    // P with 64 P = 0 mod (N4 m)
+    const bool same_m = g3.m == g4.m;
+    const unsigned gr = static_cast<unsigned>(grid);
+#define VP_SLOTS(PP)                                                                          \
+    if (same_m && period == PP) {                                                             \
+        if (diag)                                                                             \
+            velocity_reduce_slots<T, true, PP><<<gr, kRedBlock, 0, st>>>(fp, n3, n4, g3, g4,  \
+                                                                        out, nblk);           \
+        else                                                                                  \
+            velocity_reduce_slots<T, false, PP><<<gr, kRedBlock, 0, st>>>(fp, n3, n4, g3, g4, \
+                                                                         out, nblk);          \
+        return check_launch("velocity_reduce_slots");                                         \
+    }
+    VP_SLOTS(1) VP_SLOTS(2) VP_SLOTS(3) VP_SLOTS(4) VP_SLOTS(6) VP_SLOTS(8) VP_SLOTS(9)
+    VP_SLOTS(12)
+#undef VP_SLOTS
     if (diag)
-        velocity_reduce<T, true><<<static_cast<unsigned>(grid), kRedBlock, lds, st>>>(
-            fp, n3, n4, g3, g4, out, nblk);
+        velocity_reduce<T, true><<<gr, kRedBlock, lds, st>>>(fp, n3, n4, g3, g4, out, nblk);
     else
-        velocity_reduce<T, false><<<static_cast<unsigned>(grid), kRedBlock, lds, st>>>(
-            fp, n3, n4, g3, g4, out, nblk);
+        velocity_reduce<T, false><<<gr, kRedBlock, lds, st>>>(fp, n3, n4, g3, g4, out, nblk);
     return check_launch("velocity_reduce");
 }
 

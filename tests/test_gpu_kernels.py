@@ -171,10 +171,13 @@ def test_nonfinite_shift_gives_nan_line_only():
 
 @pytest.mark.parametrize("degree", [2, 1, 3, 5, -1])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-def test_density_and_moments_parity(degree, dt):
+@pytest.mark.parametrize("n4_cells", [5, 8])
+def test_density_and_moments_parity(degree, dt, n4_cells):
+    # 5 cells along v2: weights from tables; 8 cells: the weight pattern
+    # repeats within a few rounds of 64 values (register weights)
     vp = require_gpu()
     m = 1 if degree < 0 else degree + 1
-    dims = (3 * m, 2 * m, 7 * m, 5 * m)
+    dims = (3 * m, 2 * m, 7 * m, n4_cells * m)
     lo = (0.0, 0.0, -6.0, -9.0)
     ln = (4 * math.pi, 10 * math.pi, 12.0, 18.0)
     f = random_field(dims, seed=5, positive=False)
