@@ -144,75 +144,54 @@ velocity_reduce(const T* __restrict__ f, int n3, int n4, AxisGrid g3,
     }
 }
 
-// The same reductions without weight tables.  Lane l reads the elements
-// e = l + 64 t of a point's block.  When 64 P is a multiple of N4 m (m nodes
-// per cell, the period of the weights), the element in slot k = t mod P of
-// every round of P loads has the same (c mod m, e mod N4): its weight
-// W3_c W4_e and v2^2 are fixed per lane and slot, and v1 grows by the same
-// step each round.  So the weights live in registers and every value costs
-// one FMA (seven with the diagnostics).
-template <typename T, bool DIAG, int P>
+// The density without weight tables, one workgroup per point (its four
+// wavefronts interleave 64-value chunks of the block, so a point is done four
+// times sooner than by one wavefront and the last round of workgroups is
+// short).  Thread t reads the elements e = t + 256 j.  When 256 P is a
+// multiple of N4 m (m nodes per cell, the period of the weights), the
+// element in slot k = j mod P of every round of P loads has the same
+// (c mod m, e mod N4), so its weight W3_c W4_e is fixed per thread and slot:
+// the weights live in registers and every value costs one FMA.
+template <typename T, int P>
 __global__ void __launch_bounds__(kRedBlock)
-velocity_reduce_slots(const T* __restrict__ f, int n3, int n4, AxisGrid g3,
-                      AxisGrid g4, double* __restrict__ out, int64_t nblk) {
-    constexpr int kWaves = kRedBlock / 64;
-    const int lane = threadIdx.x & 63;
+density_slots(const T* __restrict__ f, int n3, int n4, AxisGrid g3, AxisGrid g4,
+              double* __restrict__ out, int64_t nblk) {
+    __shared__ double red[kRedBlock / 64];
+    const int tid = threadIdx.x;
     const int total = n3 * n4;
-    double wk[P], a1[DIAG ? P : 1], v2q[DIAG ? P : 1];
+    double wk[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) {
-        const int e = lane + 64 * k;
+        const int e = tid + kRedBlock * k;
         const int c = e / n4;
-        const int d = e - c * n4;
-        wk[k] = node_weight(g3, c) * node_weight(g4, d);
-        if (DIAG) {
-            a1[k] = node_coord(g3, c);
-            const double v2 = node_coord(g4, d);
-            v2q[k] = v2 * v2;
-        }
+        wk[k] = node_weight(g3, c) * node_weight(g4, e - c * n4);
     }
-    // rows per round of P loads, and the v1 step that goes with them
-    const int rows = 64 * P / n4;
-    const double dv1 = static_cast<double>(rows / g3.m) * g3.h;
-    for (int64_t b = static_cast<int64_t>(blockIdx.x) * kWaves + (threadIdx.x >> 6); b < nblk;
-         b += static_cast<int64_t>(gridDim.x) * kWaves) {
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
         const T* __restrict__ blk = f + b * total;
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        int it = 0;
-        for (int q0 = lane; q0 < total; q0 += 64 * P, ++it) {
+        double acc = 0.0;
+        for (int q0 = tid; q0 < total; q0 += kRedBlock * P) {
             T x[P];
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                const int q = q0 + 64 * k;
+                const int q = q0 + kRedBlock * k;
                 x[k] = blk[q < total ? q : total - 1];
             }
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                const double xv = q0 + 64 * k < total ? static_cast<double>(x[k]) : 0.0;
-                const double xw = wk[k] * xv;
-                acc[0] += xw;
-                if (DIAG) {
-                    const double v1 = fma(static_cast<double>(it), dv1, a1[k]);
-                    acc[1] = fma(wk[k], fabs(xv), acc[1]);
-                    acc[2] = fma(xw, xv, acc[2]);
-                    acc[3] = fma(xw, fma(v1, v1, v2q[k]), acc[3]);
-                }
+                const double xv = q0 + kRedBlock * k < total ? static_cast<double>(x[k]) : 0.0;
+                acc = fma(wk[k], xv, acc);
             }
         }
-        const double s0 = wave_sum64(acc[0]);
-        if (DIAG) {
-            const double s1 = wave_sum64(acc[1]);
-            const double s2 = wave_sum64(acc[2]);
-            const double s3 = wave_sum64(acc[3]);
-            if (lane == 0) {
-                out[b] = s0;
-                out[nblk + b] = s1;
-                out[2 * nblk + b] = s2;
-                out[3 * nblk + b] = s3;
-            }
-        } else if (lane == 0) {
-            out[b] = s0;
+        const double sw = wave_sum64(acc);
+        if ((tid & 63) == 0) red[tid >> 6] = sw;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < kRedBlock / 64; ++w) t += red[w];
+            out[b] = t;
         }
+        __syncthreads();
     }
 }
 
@@ -325,20 +304,18 @@ vp_status launch_reduce(bool diag, const int64_t dims[4], const void* f,
     if (grid > 8192) grid = 8192;
     // register weights when the weight pattern repeats within a few rounds
     const int64_t nm = static_cast<int64_t>(n4) * g3.m;
-    int64_t gg = 64;
+    int64_t gg = kRedBlock;
     for (int64_t a = nm; a; ) { const int64_t t = gg % a; gg = a; a = t; }
-    const int64_t period = nm / gg;    // P with 64 P = 0 mod (N4 m)
+    const int64_t period = nm / gg;    // P with 256 P = 0 mod (N4 m)
     const bool same_m = g3.m == g4.m;
     const unsigned gr = static_cast<unsigned>(grid);
+    const unsigned gp = static_cast<unsigned>(nblk);   // one workgroup per point
+    // (the density only: with the four moment sums, register weights cost
+    // more occupancy than the table lookups they save)
 #define VP_SLOTS(PP)                                                                          \
-    if (same_m && period == PP) {                                                             \
-        if (diag)                                                                             \
-            velocity_reduce_slots<T, true, PP><<<gr, kRedBlock, 0, st>>>(fp, n3, n4, g3, g4,  \
-                                                                        out, nblk);           \
-        else                                                                                  \
-            velocity_reduce_slots<T, false, PP><<<gr, kRedBlock, 0, st>>>(fp, n3, n4, g3, g4, \
-                                                                         out, nblk);          \
-        return check_launch("velocity_reduce_slots");                                         \
+    if (!diag && same_m && period == PP) {                                                    \
+        density_slots<T, PP><<<gp, kRedBlock, 0, st>>>(fp, n3, n4, g3, g4, out, nblk);        \
+        return check_launch("density_slots");                                                 \
     }
     VP_SLOTS(1) VP_SLOTS(2) VP_SLOTS(3) VP_SLOTS(4) VP_SLOTS(6) VP_SLOTS(8) VP_SLOTS(9)
     VP_SLOTS(12)
