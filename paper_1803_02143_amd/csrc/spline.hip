@@ -306,16 +306,32 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     const bool active = l < nl && b < e;
     const T* __restrict__ src = fin + lbase;
     if (active) {
-        // batches of kU independent loads keep many requests in flight
-        int i = b;
-        for (; i + kU <= e; i += kU) {
-            T v[kU];
+        if constexpr (sizeof(T) == 8) {
+            // FP64: the whole 24-point segment's loads in flight at once
+            // (the tile size already limits the occupancy), clamped indices,
+            // only the LDS stores guarded
+            constexpr int kSeg = 24;
+            for (int i0 = b; i0 < e; i0 += kSeg) {
+                T v[kSeg];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) v[u] = src[static_cast<int64_t>(i + u) * inner];
+                for (int u = 0; u < kSeg; ++u)
+                    v[u] = src[static_cast<int64_t>(min(i0 + u, e - 1)) * inner];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) buf[(i + u) * L + l] = v[u];
+                for (int u = 0; u < kSeg; ++u)
+                    if (i0 + u < e) buf[(i0 + u) * L + l] = v[u];
+            }
+        } else {
+            // FP32: batches of kU loads (registers limit the occupancy here)
+            int i = b;
+            for (; i + kU <= e; i += kU) {
+                T v[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) v[u] = src[static_cast<int64_t>(i + u) * inner];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) buf[(i + u) * L + l] = v[u];
+            }
+            for (; i < e; ++i) buf[i * L + l] = src[static_cast<int64_t>(i) * inner];
         }
-        for (; i < e; ++i) buf[i * L + l] = src[static_cast<int64_t>(i) * inner];
     }
     // shift derivative: the thread's segment of lam, in flight during the
     // solve (clamped indices, no branches between the loads)
