@@ -375,11 +375,11 @@ vp_status launch_sldg(int axis, const int64_t dims[4], const void* fin,
         }
         return check_launch("sldg_col");
     }
-    // rows per workgroup: one full round of the cell loop (4 or 2 cells per
-    // thread; two rounds in FP32, so that the operator build is spread over
-    // as many bytes as in FP64), the R operators in LDS
+    // rows per workgroup: two rounds of the cell loop (4 or 2 cells per
+    // thread per round), so that the operator build is spread over enough
+    // bytes; the R operators in LDS
     const size_t per_row = static_cast<size_t>(2 * M * M) * sizeof(T) + sizeof(int);
-    int R = (M <= 3 ? 4 : 2) * (sizeof(T) == 4 ? 2 : 1) * kBlock / nc;
+    int R = (M <= 3 ? 4 : 2) * 2 * kBlock / nc;
     if (R < 1) R = 1;
     if (R > kBlock) R = kBlock;
     const size_t lds = R * per_row;
