@@ -101,6 +101,26 @@ def test_spline_and_field_argument_errors():
     assert lib.vp_strang_step(None, pa, pb, 1, 0.1, None, None, None) == L.VP_ERR_ARG
 
 
+def test_adjoint_and_run_argument_errors():
+    L, lib = _lib()
+    dims = L.i64x4((6, 6, 6, 6))
+    st = L.i64x4((0, 0, 1, 0))
+    a, b, s, g = _fake(), _fake(), _fake(), _fake()
+    pa, pb, ps, pg = (ctypes.cast(x, ctypes.c_void_p) for x in (a, b, s, g))
+    assert lib.sldg_advect_adjoint(5, 2, L.VP_F64, dims, pa, pb, ps, st, None) == L.VP_ERR_ARG
+    assert lib.sldg_advect_adjoint(0, 2, L.VP_F64, dims, pa, pa, ps, st, None) == L.VP_ERR_ALIAS
+    assert lib.sldg_advect_dshift(0, 2, L.VP_F64, dims, pa, pb, ps, st, None, None) == L.VP_ERR_ARG
+    assert lib.spline_advect_adjoint(0, L.VP_F64, dims, pa, pa, ps, st, None) == L.VP_ERR_ALIAS
+    assert lib.spline_advect_dshift(0, 7, dims, pa, pb, ps, st, pg, None) == L.VP_ERR_ARG
+    assert lib.vp_density_adjoint(2, L.VP_F64, dims, None, 1.0, 1.0, pa, 0, None) == L.VP_ERR_ARG
+    assert lib.vp_density_adjoint(2, L.VP_F64, dims, pb, 0.0, 1.0, pa, 0, None) == L.VP_ERR_ARG
+    ws = lib.vp_poisson_workspace(2, 6, 6)
+    assert lib.vp_poisson_adjoint(2, 6, 6, 1.0, 1.0, pa, pb, pa, pg, ws, None) == L.VP_ERR_ALIAS
+    assert lib.vp_strang_adjoint(None, pa, pb, 0.1, pg, 1 << 20, None) == L.VP_ERR_ARG
+    assert lib.vp_energy_gradient(None, pa, pb, None, None) == L.VP_ERR_ARG
+    assert lib.vp_strang_run(None, pa, pb, 4, 0.1, 2, None, None, None) == L.VP_ERR_ARG
+
+
 def test_binding_fails_loudly_without_library(tmp_path):
     from paper_1803_02143_amd import _lib as L
     saved = L._LIB
