@@ -192,6 +192,11 @@ VP4D_API void vp_destroy(vp_state* st);
  *   W_trace  device, nsteps+1 doubles or NULL: W of f^m ... f^{m+nsteps}.
  *   moments  device, 4*(nsteps+1) doubles or NULL: mass, L1, L2, kinetic
  *            energy of the same states.
+ * When N3*N4 is a multiple of 256 (SLDG) or of 64 with 64-line spline tiles
+ * (N2 * 64 * sizeof(T) <= 48 KiB), the x2 sweep that precedes each field
+ * solve also forms the density of its output, and the separate read of f
+ * for rho is skipped; rho then differs from vp_density only in the order of
+ * its FP64 additions.
  */
 VP4D_API vp_status vp_strang_step(vp_state* st, void* f, void* f_tmp, int nsteps,
                          double tau, double* W_trace, double* moments,
@@ -303,15 +308,16 @@ VP4D_API vp_status vp_strang_adjoint(vp_state* st, const void* f, void* lam, dou
                             void* work, size_t ws_bytes, void* stream);
 
 /*
- * Kernel timers of a vp_state.  When enabled, vp_strang_step records HIP
- * events around its launches on `stream`.  vp_timing_read synchronises the
+ * Kernel timers of a vp_state.  When enabled, vp_strang_step and
+ * vp_strang_run record HIP events around their launches on `stream`.  vp_timing_read synchronises the
  * events recorded so far, adds their durations per category into ms[] and
  * counts[] (VP_TIMER_COUNT entries each, both host) and clears them.
  */
 enum {
     VP_TIMER_SWEEP_X1 = 0, VP_TIMER_SWEEP_X2 = 1, VP_TIMER_SWEEP_V1 = 2,
     VP_TIMER_SWEEP_V2 = 3, VP_TIMER_FIELD = 4, VP_TIMER_DIAG = 5,
-    VP_TIMER_COUNT = 6
+    VP_TIMER_SWEEP_X2_RHO = 6,  /* x2 sweeps that also form the density */
+    VP_TIMER_COUNT = 7
 };
 VP4D_API vp_status vp_timing_enable(vp_state* st, int enable);
 VP4D_API vp_status vp_timing_read(vp_state* st, double* ms, int64_t* counts);

@@ -21,8 +21,9 @@ STATUS_NAMES = {0: "VP_OK", -1: "VP_ERR_ARG", -2: "VP_ERR_UNSUPPORTED",
 
 VP_F32 = 0
 VP_F64 = 1
-VP_TIMER_COUNT = 6
-TIMER_NAMES = ("sweep_x1", "sweep_x2", "sweep_v1", "sweep_v2", "field", "diag")
+VP_TIMER_COUNT = 7
+TIMER_NAMES = ("sweep_x1", "sweep_x2", "sweep_v1", "sweep_v2", "field", "diag",
+               "sweep_x2_rho")
 
 _i64x4 = ctypes.c_int64 * 4
 _dblx4 = ctypes.c_double * 4

@@ -195,6 +195,35 @@ density_slots(const T* __restrict__ f, int n3, int n4, AxisGrid g3, AxisGrid g4,
     }
 }
 
+// rho[a][j] = sum over the groups g of part[(a * groups + g) * n2 + j]:
+// workgroup (j-block, a), lane -> j, wavefront w sums the groups g = w mod 4
+// (four independent accumulators each), the four partial sums meet in LDS.
+// A fixed order, so the result is reproducible.
+__global__ void __launch_bounds__(256)
+rho_from_parts(const double* __restrict__ part, int64_t groups, int64_t n2,
+               double* __restrict__ rho) {
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t a = blockIdx.y;
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+    const int64_t jc = j < n2 ? j : n2 - 1;
+    const double* __restrict__ p = part + a * groups * n2 + jc;
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    int64_t g = wave;
+    for (; g + 12 < groups; g += 16) {
+        t0 += p[g * n2];
+        t1 += p[(g + 4) * n2];
+        t2 += p[(g + 8) * n2];
+        t3 += p[(g + 12) * n2];
+    }
+    for (; g < groups; g += 4) t0 += p[g * n2];
+    red[wave][lane] = (t0 + t1) + (t2 + t3);
+    __syncthreads();
+    if (wave == 0 && j < n2)
+        rho[a * n2 + j] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
 constexpr int kFinalBlock = 1024;
 
 // out4 = (mass, L1, L2, kinetic) from the per-(x1,x2) partial sums.
@@ -328,6 +357,13 @@ vp_status launch_reduce(bool diag, const int64_t dims[4], const void* f,
 }
 
 }  // namespace
+
+vp_status rho_from_parts_impl(const double* part, int64_t n1, int64_t groups, int64_t n2,
+                              double* rho, hipStream_t st) {
+    const dim3 grid(static_cast<unsigned>((n2 + 63) / 64), static_cast<unsigned>(n1));
+    rho_from_parts<<<grid, 256, 0, st>>>(part, groups, n2, rho);
+    return check_launch("rho_from_parts");
+}
 
 vp_status density_impl(int degree, vp_dtype dt, const int64_t dims[4],
                        const void* f, double len_v1, double len_v2, double* rho,

@@ -21,6 +21,30 @@ AxisGrid axis_grid(int degree, int64_t n, double lo, double len);
 vp_status check_grid_args(int degree, vp_dtype dt, const int64_t dims[4],
                           int64_t* total);
 
+// Density of the output of an x2 sweep, formed inside the sweep: every
+// group of adjacent velocity columns that a workgroup (or wavefront) owns
+// adds W3 W4 f_out over its columns into part[(x1 * groups + g) * N2 + j],
+// and rho_from_parts sums the groups in a fixed order.
+struct RhoFuse {
+    double* part;    // device, x1 * groups * N2 doubles
+    AxisGrid g3, g4; // velocity node weights
+    int n4;          // N4 (v2 nodes), to split the column index
+};
+// Velocity columns per group of the fused spline x2 sweep (0: no fused
+// path for this grid); the SLDG one uses groups of 256 columns when N3 N4 is
+// a multiple of 256.
+int spline_rho_group(vp_dtype dt, const int64_t dims[4]);
+vp_status sldg_advect_rho_impl(int degree, vp_dtype dt, const int64_t dims[4],
+                               const void* f_in, void* f_out, const double* shift,
+                               const int64_t shift_stride[4], const RhoFuse& rf,
+                               hipStream_t st);
+vp_status spline_advect_rho_impl(vp_dtype dt, const int64_t dims[4], const void* f_in,
+                                 void* f_out, const double* shift,
+                                 const int64_t shift_stride[4], const RhoFuse& rf,
+                                 hipStream_t st);
+vp_status rho_from_parts_impl(const double* part, int64_t n1, int64_t groups, int64_t n2,
+                              double* rho, hipStream_t st);
+
 // Sweep (adjoint = false) or its transpose for fixed shifts (adjoint = true).
 vp_status sldg_advect_impl(int axis, int degree, vp_dtype dt,
                            const int64_t dims[4], const void* f_in, void* f_out,

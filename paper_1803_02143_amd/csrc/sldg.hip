@@ -30,7 +30,7 @@
 // uses dA/dalpha and dB/dalpha from Leibniz' rule on the defining integrals:
 //   A'_jl = (1/w_j)[L_l(1) L_j(alpha) - sum_q alpha w_q L_l'(alpha xi_q + 1 - alpha) L_j(alpha xi_q)]
 //   B'_jl = (1/w_j)[-L_l(0) L_j(alpha) - sum_q (1-alpha) w_q L_l'((1-alpha) xi_q) L_j(alpha + (1-alpha) xi_q)]
-#include "vp4d_internal.hpp"
+#include "field.hpp"
 
 namespace vp {
 namespace {
@@ -267,6 +267,122 @@ sldg_col(const T* __restrict__ fin, T* __restrict__ fout,
     }
 }
 
+// The x2 sweep with its output density formed on the way (forward only).
+// Output cells are produced in order, every lane of a wavefront on the same
+// cell: output i is fed by input cells (l0 + i, l0 + i + 1) mod n_c with
+// l0 = n_c - 1 - s, which lanes load from their own (shift-dependent) rows.
+// The weighted values W3 W4 f_out of CU cells are reduce-scattered across
+// the wavefront; the four wavefronts' sums meet in LDS, and each workgroup
+// writes the partial density of its 256 velocity columns (inner must be a
+// multiple of the workgroup size).  Every input cell is loaded once.
+template <int M, typename T>
+__global__ void __launch_bounds__(kBlock)
+sldg_col_rho(const T* __restrict__ fin, T* __restrict__ fout,
+             const double* __restrict__ shift, ShiftMap sm, int nc, int64_t inner,
+             NodeBasis basis, RhoFuse rf) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = nc * M;
+    double* rp = reinterpret_cast<double*>(smem);   // [kBlock / 64][N]
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const int64_t o = gid / inner;
+    const int64_t k = gid - o * inner;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int v1 = static_cast<int>(k / rf.n4);
+    const int v2 = static_cast<int>(k - static_cast<int64_t>(v1) * rf.n4);
+    const double wk = rf.g3.w[v1 % rf.g3.m] * rf.g3.h * (rf.g4.w[v2 % rf.g4.m] * rf.g4.h);
+
+    int s;
+    T A[M][M], B[M][M];
+    sldg_operator<M, T>(basis, shift[shift_offset(sm, o, k)], nc, s, A, B);
+    const int64_t cs = static_cast<int64_t>(M) * inner;
+    const T* __restrict__ src = fin + o * nc * cs + k;
+    T* __restrict__ dst = fout + o * nc * cs + k;
+
+    const int l0 = nc - 1 - s;
+    T first[M], prev[M];
+#pragma unroll
+    for (int l = 0; l < M; ++l) {
+        first[l] = src[l0 * cs + l * inner];
+        prev[l] = first[l];
+    }
+    int rc = l0 + 1 == nc ? 0 : l0 + 1;   // next input cell to load
+    constexpr int CU = M <= 3 ? 4 : 2;          // cells whose loads are in flight together
+    constexpr int V = 2 * M <= 4 ? 4 : (2 * M <= 8 ? 8 : 16);   // two cells per reduction
+    int i = 0;
+    for (; i + CU <= nc - 1; i += CU) {
+        T cur[CU][M];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            int c = rc + u;
+            c -= c >= nc ? nc : 0;
+#pragma unroll
+            for (int l = 0; l < M; ++l) cur[u][l] = src[c * cs + l * inner];
+        }
+#pragma unroll
+        for (int h = 0; h < CU; h += 2) {
+            double vals[V];
+#pragma unroll
+            for (int t = 0; t < V; ++t) vals[t] = 0.0;
+#pragma unroll
+            for (int u = h; u < h + 2; ++u) {
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    T acc = T(0);
+#pragma unroll
+                    for (int l = 0; l < M; ++l) acc = fma(A[j][l], prev[l], acc);
+#pragma unroll
+                    for (int l = 0; l < M; ++l) acc = fma(B[j][l], cur[u][l], acc);
+                    dst[(i + u) * cs + j * inner] = acc;
+                    vals[(u - h) * M + j] = wk * static_cast<double>(acc);
+                }
+#pragma unroll
+                for (int l = 0; l < M; ++l) prev[l] = cur[u][l];
+            }
+            const double r = group_reduce_scatter<V, 64>(vals, lane);
+            if (lane < 2 * M) rp[wave * N + (i + h) * M + lane] = r;
+        }
+        rc += CU;
+        rc -= rc >= nc ? nc : 0;
+    }
+    constexpr int VT = M <= 4 ? 4 : 8;
+    for (; i < nc; ++i) {
+        T cur[M];
+        if (i < nc - 1) {
+#pragma unroll
+            for (int l = 0; l < M; ++l) cur[l] = src[rc * cs + l * inner];
+        } else {
+#pragma unroll
+            for (int l = 0; l < M; ++l) cur[l] = first[l];
+        }
+        double vals[VT];
+#pragma unroll
+        for (int t = 0; t < VT; ++t) vals[t] = 0.0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            T acc = T(0);
+#pragma unroll
+            for (int l = 0; l < M; ++l) acc = fma(A[j][l], prev[l], acc);
+#pragma unroll
+            for (int l = 0; l < M; ++l) acc = fma(B[j][l], cur[l], acc);
+            dst[i * cs + j * inner] = acc;
+            vals[j] = wk * static_cast<double>(acc);
+        }
+        const double r = group_reduce_scatter<VT, 64>(vals, lane);
+        if (lane < M) rp[wave * N + i * M + lane] = r;
+#pragma unroll
+        for (int l = 0; l < M; ++l) prev[l] = cur[l];
+        rc = rc + 1 == nc ? 0 : rc + 1;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < N; j += kBlock) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) t += rp[w * N + j];
+        rf.part[static_cast<int64_t>(blockIdx.x) * N + j] = t;
+    }
+}
+
 template <int M, typename T, bool ADJ>
 __global__ void __launch_bounds__(kBlock)
 sldg_row(const T* __restrict__ fin, T* __restrict__ fout,
@@ -399,6 +515,37 @@ vp_status dispatch_degree(int degree, int axis, const int64_t dims[4],
         case 3: return launch_sldg<4, T, ADJ>(axis, dims, fin, fout, shift, sm, st);
         case 4: return launch_sldg<5, T, ADJ>(axis, dims, fin, fout, shift, sm, st);
         case 5: return launch_sldg<6, T, ADJ>(axis, dims, fin, fout, shift, sm, st);
+        default: return set_error(VP_ERR_UNSUPPORTED, "degree %d", degree);
+    }
+}
+
+template <int M, typename T>
+vp_status launch_sldg_rho(const int64_t dims[4], const void* fin, void* fout,
+                          const double* shift, const ShiftMap& sm, const RhoFuse& rf,
+                          hipStream_t st) {
+    const NodeBasis& b = node_basis(M - 1);
+    const int64_t outer = dims[0];
+    const int64_t inner = dims[2] * dims[3];
+    const int nc = static_cast<int>(dims[1] / M);
+    const size_t lds = sizeof(double) * (kBlock / 64) * static_cast<size_t>(dims[1]);
+    if (inner % kBlock || lds > 48 * 1024)
+        return set_error(VP_ERR_UNSUPPORTED, "fused x2 sweep needs whole workgroups of columns");
+    sldg_col_rho<M, T><<<blocks_for(outer * inner, kBlock), kBlock, lds, st>>>(
+        static_cast<const T*>(fin), static_cast<T*>(fout), shift, sm, nc, inner, b, rf);
+    return check_launch("sldg_col_rho");
+}
+
+template <typename T>
+vp_status dispatch_rho(int degree, const int64_t dims[4], const void* fin, void* fout,
+                       const double* shift, const ShiftMap& sm, const RhoFuse& rf,
+                       hipStream_t st) {
+    switch (degree) {
+        case 0: return launch_sldg_rho<1, T>(dims, fin, fout, shift, sm, rf, st);
+        case 1: return launch_sldg_rho<2, T>(dims, fin, fout, shift, sm, rf, st);
+        case 2: return launch_sldg_rho<3, T>(dims, fin, fout, shift, sm, rf, st);
+        case 3: return launch_sldg_rho<4, T>(dims, fin, fout, shift, sm, rf, st);
+        case 4: return launch_sldg_rho<5, T>(dims, fin, fout, shift, sm, rf, st);
+        case 5: return launch_sldg_rho<6, T>(dims, fin, fout, shift, sm, rf, st);
         default: return set_error(VP_ERR_UNSUPPORTED, "degree %d", degree);
     }
 }
@@ -600,6 +747,16 @@ vp_status sldg_advect_impl(int axis, int degree, vp_dtype dt,
     return adjoint
                ? dispatch_degree<float, true>(degree, axis, dims, f_in, f_out, shift, sm, st)
                : dispatch_degree<float, false>(degree, axis, dims, f_in, f_out, shift, sm, st);
+}
+
+vp_status sldg_advect_rho_impl(int degree, vp_dtype dt, const int64_t dims[4],
+                               const void* f_in, void* f_out, const double* shift,
+                               const int64_t shift_stride[4], const RhoFuse& rf,
+                               hipStream_t st) {
+    const ShiftMap sm = make_shift_map(1, dims, shift_stride);
+    if (dt == VP_F64)
+        return dispatch_rho<double>(degree, dims, f_in, f_out, shift, sm, rf, st);
+    return dispatch_rho<float>(degree, dims, f_in, f_out, shift, sm, rf, st);
 }
 
 vp_status sldg_dshift_impl(int axis, int degree, vp_dtype dt, const int64_t dims[4],

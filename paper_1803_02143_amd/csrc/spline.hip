@@ -23,7 +23,7 @@
 // store element-parallel with contiguous global accesses.
 #include <cmath>
 
-#include "vp4d_internal.hpp"
+#include "field.hpp"
 
 namespace vp {
 namespace {
@@ -205,7 +205,9 @@ __device__ __forceinline__ int first_tap(int i, int s, int n) {
     return j;
 }
 
-enum { kFwd = 0, kAdj = 1, kDshift = 2 };
+// kFwdRho: the forward sweep that also writes the partial density of its
+// output (x2 sweeps with 64-line tiles; the workgroup's 64 columns)
+enum { kFwd = 0, kAdj = 1, kDshift = 2, kFwdRho = 3 };
 
 // Longest segment a thread owns: tiles hold at most kTileBytes, so a
 // segment has at most kTileBytes / (kBlock * sizeof(T)) points.
@@ -283,7 +285,8 @@ template <typename T, int AXIS, int MODE>
 __global__ void __launch_bounds__(kBlock)
 spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ lam,
            double* __restrict__ g, const double* __restrict__ shift, ShiftMap sm,
-           int64_t nlines, int64_t inner, int L, SplineParams<T> sp) {
+           int64_t nlines, int64_t inner, int L, SplineParams<T> sp, RhoFuse rf) {
+    constexpr bool FWD = MODE == kFwd || MODE == kFwdRho;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[MODE == kDshift ? kBlock : 1];
     const int n = sp.n;
@@ -380,16 +383,35 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         j = next_idx(j, n);
         T c3 = buf[j * L + l];
         int i = b;
-        if (MODE == kFwd) {
+        // density weight of this line's velocity column (kFwdRho)
+        double wk = 0.0;
+        if (MODE == kFwdRho) {
+            const int v1 = static_cast<int>(kl / rf.n4);
+            const int v2 = static_cast<int>(kl - static_cast<int64_t>(v1) * rf.n4);
+            wk = rf.g3.w[v1 % rf.g3.m] * rf.g3.h * (rf.g4.w[v2 % rf.g4.m] * rf.g4.h);
+        }
+        if (FWD) {
             for (; i + 4 <= e; i += 4) {
                 const int j4 = next_idx(j, n), j5 = next_idx(j4, n);
                 const int j6 = next_idx(j5, n), j7 = next_idx(j6, n);
                 const T c4 = buf[j4 * L + l], c5 = buf[j5 * L + l];
                 const T c6 = buf[j6 * L + l], c7 = buf[j7 * L + l];
-                dst[static_cast<int64_t>(i) * inner] = fma(w3, c3, fma(w2, c2, fma(w1, c1, w0 * c0)));
-                dst[static_cast<int64_t>(i + 1) * inner] = fma(w3, c4, fma(w2, c3, fma(w1, c2, w0 * c1)));
-                dst[static_cast<int64_t>(i + 2) * inner] = fma(w3, c5, fma(w2, c4, fma(w1, c3, w0 * c2)));
-                dst[static_cast<int64_t>(i + 3) * inner] = fma(w3, c6, fma(w2, c5, fma(w1, c4, w0 * c3)));
+                const T o0 = fma(w3, c3, fma(w2, c2, fma(w1, c1, w0 * c0)));
+                const T o1 = fma(w3, c4, fma(w2, c3, fma(w1, c2, w0 * c1)));
+                const T o2 = fma(w3, c5, fma(w2, c4, fma(w1, c3, w0 * c2)));
+                const T o3 = fma(w3, c6, fma(w2, c5, fma(w1, c4, w0 * c3)));
+                dst[static_cast<int64_t>(i) * inner] = o0;
+                dst[static_cast<int64_t>(i + 1) * inner] = o1;
+                dst[static_cast<int64_t>(i + 2) * inner] = o2;
+                dst[static_cast<int64_t>(i + 3) * inner] = o3;
+                if (MODE == kFwdRho) {
+                    // the wavefront's 64 lines share i: sums over them
+                    double vals[4] = {wk * static_cast<double>(o0), wk * static_cast<double>(o1),
+                                      wk * static_cast<double>(o2), wk * static_cast<double>(o3)};
+                    const double r = group_reduce_scatter<4, 64>(vals, threadIdx.x & 63);
+                    if ((threadIdx.x & 63) < 4)
+                        rf.part[static_cast<int64_t>(blockIdx.x) * n + i + (threadIdx.x & 63)] = r;
+                }
                 c0 = c4;
                 c1 = c5;
                 c2 = c6;
@@ -397,10 +419,15 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                 j = j7;
             }
         }
-        if (MODE == kFwd) {
+        if (FWD) {
             for (; i < e; ++i) {
-                dst[static_cast<int64_t>(i) * inner] =
-                    fma(w3, c3, fma(w2, c2, fma(w1, c1, w0 * c0)));
+                const T o = fma(w3, c3, fma(w2, c2, fma(w1, c1, w0 * c0)));
+                dst[static_cast<int64_t>(i) * inner] = o;
+                if (MODE == kFwdRho) {
+                    double vals[1] = {wk * static_cast<double>(o)};
+                    const double r = group_reduce_scatter<1, 64>(vals, threadIdx.x & 63);
+                    if ((threadIdx.x & 63) == 0) rf.part[static_cast<int64_t>(blockIdx.x) * n + i] = r;
+                }
                 c0 = c1;
                 c1 = c2;
                 c2 = c3;
@@ -615,10 +642,17 @@ SplineParams<T> make_params(int n) {
 
 constexpr size_t kTileBytes = 48 * 1024;
 
+// lines per column tile: a power of two up to 64 within the LDS budget
+int tile_lines(int n, size_t esize) {
+    int L = 64;
+    while (L > 1 && static_cast<size_t>(n) * L * esize > kTileBytes) L /= 2;
+    return L;
+}
+
 template <typename T, int MODE>
 vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
                         void* fout, const void* lam, double* g, const double* shift,
-                        const ShiftMap& sm, hipStream_t st) {
+                        const ShiftMap& sm, hipStream_t st, const RhoFuse& rf = RhoFuse{}) {
     int64_t outer = 1, inner = 1;
     for (int d = 0; d < axis; ++d) outer *= dims[d];
     for (int d = axis + 1; d < 4; ++d) inner *= dims[d];
@@ -628,11 +662,11 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
     T* out = static_cast<T*>(fout);
     const T* lm = static_cast<const T*>(lam);
     if (axis < 3) {
-        // lines per tile: a power of two up to 64 within the LDS budget; tiles
-        // run over the flattened line index
-        int L = 64;
-        while (L > 1 && static_cast<size_t>(n) * L * sizeof(T) > kTileBytes) L /= 2;
+        // tiles run over the flattened line index
+        const int L = tile_lines(n, sizeof(T));
         const size_t lds = static_cast<size_t>(n) * L * sizeof(T);
+        if (MODE == kFwdRho && (axis != 1 || L != 64 || inner % 64))
+            return set_error(VP_ERR_UNSUPPORTED, "fused x2 sweep needs 64-line tiles");
         if (lds > kTileBytes)
             return set_error(VP_ERR_UNSUPPORTED,
                              "spline_advect: line of %d points too long for the LDS tile", n);
@@ -641,19 +675,26 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
         if (grid64 >= (int64_t(1) << 31))
             return set_error(VP_ERR_UNSUPPORTED, "spline_advect: grid too large");
         const unsigned grid = static_cast<unsigned>(grid64);
-        switch (axis) {
-            case 0:
-                spline_col<T, 0, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp);
-                break;
-            case 1:
-                spline_col<T, 1, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp);
-                break;
-            default:
-                spline_col<T, 2, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp);
-                break;
+        if constexpr (MODE == kFwdRho) {
+            spline_col<T, 1, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
+        } else {
+            switch (axis) {
+                case 0:
+                    spline_col<T, 0, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
+                    break;
+                case 1:
+                    spline_col<T, 1, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
+                    break;
+                default:
+                    spline_col<T, 2, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
+                    break;
+            }
         }
         return check_launch("spline_col");
     }
+    if constexpr (MODE == kFwdRho) {
+        return set_error(VP_ERR_UNSUPPORTED, "fused density only on x2 sweeps");
+    } else {
     // rows per tile: a power of two (so every segment fits SegMax) within
     // the LDS budget
     int R = 64;
@@ -669,6 +710,7 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
     spline_row<T, MODE><<<static_cast<unsigned>(grid64), kBlock, lds, st>>>(in, out, lm, g, shift,
                                                                           sm, outer, R, sp);
     return check_launch("spline_row");
+    }
 }
 
 }  // namespace
@@ -682,6 +724,23 @@ vp_status spline_advect_impl(int axis, vp_dtype dt, const int64_t dims[4],
                        : launch_spline<double, kFwd>(axis, dims, f_in, f_out, nullptr, nullptr, shift, sm, st);
     return adjoint ? launch_spline<float, kAdj>(axis, dims, f_in, f_out, nullptr, nullptr, shift, sm, st)
                    : launch_spline<float, kFwd>(axis, dims, f_in, f_out, nullptr, nullptr, shift, sm, st);
+}
+
+vp_status spline_advect_rho_impl(vp_dtype dt, const int64_t dims[4], const void* f_in,
+                                 void* f_out, const double* shift,
+                                 const int64_t shift_stride[4], const RhoFuse& rf,
+                                 hipStream_t st) {
+    const ShiftMap sm = make_shift_map(1, dims, shift_stride);
+    if (dt == VP_F64)
+        return launch_spline<double, kFwdRho>(1, dims, f_in, f_out, nullptr, nullptr, shift, sm,
+                                              st, rf);
+    return launch_spline<float, kFwdRho>(1, dims, f_in, f_out, nullptr, nullptr, shift, sm, st,
+                                         rf);
+}
+
+int spline_rho_group(vp_dtype dt, const int64_t dims[4]) {
+    const int L = tile_lines(static_cast<int>(dims[1]), dtype_size(dt));
+    return L == 64 && (dims[2] * dims[3]) % 64 == 0 ? 64 : 0;
 }
 
 vp_status spline_dshift_impl(int axis, vp_dtype dt, const int64_t dims[4], const void* f_in,

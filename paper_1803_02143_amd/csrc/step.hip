@@ -26,6 +26,8 @@ struct vp_state {
     double* buf;  // one device allocation holding every 2D array below
     double *rho, *e1, *e2, *sig_v1, *sig_v2, *sig_x1, *sig_x2, *vnode1, *vnode2;
     double *sig_x1f, *sig_x2f;  // x shifts of a whole step (merged half-steps)
+    double* rho_part;           // partial densities of the fused x2 sweep
+    int64_t rho_groups;         // column groups per x1 (0: no fused x2 sweep)
     double* partial;  // 4 * n1 * n2
     double *gs1, *gs2, *rho_bar;  // adjoint: shift gradients and transposed density
     void* pws;        // Poisson workspace
@@ -88,6 +90,37 @@ vp_status sweep(vp_state* st, int axis, const void* in, void* out,
                                             stride, s, adjoint);
     if (!adjoint) mark(st, VP_TIMER_SWEEP_X1 + axis, s);
     return rc;
+}
+
+// The x2 sweep of a state whose density comes next: when the grid allows
+// it, the sweep also writes the partial densities of its output (and the
+// field then sums them instead of reading the state again).
+vp_status sweep_x2_rho(vp_state* st, const void* in, void* out, const double* shift,
+                       hipStream_t s, bool& fused) {
+    fused = st->rho_groups > 0;
+    if (!fused) return sweep(st, 1, in, out, shift, s);
+    int64_t stride[4];
+    step_strides(st, 1, stride);
+    RhoFuse rf{};
+    rf.part = st->rho_part;
+    rf.g3 = axis_grid(st->degree, st->dims[2], st->lo[2], st->len[2]);
+    rf.g4 = axis_grid(st->degree, st->dims[3], st->lo[3], st->len[3]);
+    rf.n4 = static_cast<int>(st->dims[3]);
+    mark(st, VP_TIMER_SWEEP_X2_RHO, s);
+    vp_status rc = st->method == 0
+                       ? sldg_advect_rho_impl(st->degree, st->dt, st->dims, in, out, shift,
+                                              stride, rf, s)
+                       : spline_advect_rho_impl(st->dt, st->dims, in, out, shift, stride, rf, s);
+    mark(st, VP_TIMER_SWEEP_X2_RHO, s);
+    return rc;
+}
+
+// rho of the state f: from the fused sweep's partials, or a read of f.
+vp_status density_of(vp_state* st, const void* f, bool fused, hipStream_t s) {
+    if (fused)
+        return rho_from_parts_impl(st->rho_part, st->dims[0], st->rho_groups, st->dims[1],
+                                   st->rho, s);
+    return density_impl(st->degree, st->dt, st->dims, f, st->len[2], st->len[3], st->rho, s);
 }
 
 vp_status dshift(vp_state* st, int axis, const void* f, const void* lam,
@@ -172,8 +205,16 @@ extern "C" vp_status vp_create(vp_state** out, int method, int degree, vp_dtype 
     }
     const int64_t nx = dims[0] * dims[1];
     const size_t pws = vp_poisson_workspace(deg, dims[0], dims[1]);
+    // the x2 sweep forms the density of its output in groups of velocity
+    // columns: 256 per workgroup for SLDG, 64 per tile for the spline
+    const int64_t nvel = dims[2] * dims[3];
+    int64_t groups = 0;
+    if (method == 0 && nvel % 256 == 0) groups = nvel / 256;
+    if (method == 1 && spline_rho_group(dt, dims) > 0) groups = nvel / spline_rho_group(dt, dims);
+    const size_t npart = static_cast<size_t>(dims[0] * groups * dims[1]);
     const size_t ndbl = static_cast<size_t>(nx) * (5 + 4 + 3) +
-                        3 * static_cast<size_t>(dims[2] + dims[3]) + pws / sizeof(double) + 64;
+                        3 * static_cast<size_t>(dims[2] + dims[3]) + pws / sizeof(double) + 64 +
+                        npart + 32;
     void* mem = nullptr;
     hipError_t e = hipMalloc(&mem, ndbl * sizeof(double));
     if (e != hipSuccess) {
@@ -198,6 +239,9 @@ extern "C" vp_status vp_create(vp_state** out, int method, int degree, vp_dtype 
     st->vnode2 = p; p += dims[3];
     st->sig_x1f = p; p += dims[2];
     st->sig_x2f = p; p += dims[3];
+    st->rho_groups = groups;
+    st->rho_part = p;
+    p += npart;
     p = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(p) + 255) & ~uintptr_t(255));
     st->pws = p;
     // velocity node coordinates, used for the x-sweep shifts
@@ -263,12 +307,12 @@ vp_status strang_run(vp_state* st, void* f, void* f_tmp, int nsteps, double tau,
     const bool diag = W_trace || moments;
     if (diag && (rc = diagnostics(st, f, W_trace, moments, s)) != VP_OK) return rc;
     for (int seg = 0; seg < nsteps / every; ++seg) {
+        bool fused = false;
         if ((rc = sweep(st, 0, f, f_tmp, st->sig_x1, s)) != VP_OK) return rc;
-        if ((rc = sweep(st, 1, f_tmp, f, st->sig_x2, s)) != VP_OK) return rc;
+        if ((rc = sweep_x2_rho(st, f_tmp, f, st->sig_x2, s, fused)) != VP_OK) return rc;
         for (int j = 0; j < every; ++j) {
             mark(st, VP_TIMER_FIELD, s);
-            rc = density_impl(st->degree, st->dt, st->dims, f, st->len[2], st->len[3],
-                              st->rho, s);
+            rc = density_of(st, f, fused, s);
             // E of the current state and the v-sweep shifts tau E_d / h_{v_d}
             if (rc == VP_OK)
                 rc = poisson_impl_shift(st->degree, st->dims[0], st->dims[1], st->len[0],
@@ -282,8 +326,11 @@ vp_status strang_run(vp_state* st, void* f, void* f_tmp, int nsteps, double tau,
             const bool last = j == every - 1;
             if ((rc = sweep(st, 0, f, f_tmp, last ? st->sig_x1 : st->sig_x1f, s)) != VP_OK)
                 return rc;
-            if ((rc = sweep(st, 1, f_tmp, f, last ? st->sig_x2 : st->sig_x2f, s)) != VP_OK)
-                return rc;
+            if (last)
+                rc = sweep(st, 1, f_tmp, f, st->sig_x2, s);
+            else
+                rc = sweep_x2_rho(st, f_tmp, f, st->sig_x2f, s, fused);
+            if (rc != VP_OK) return rc;
         }
         if (diag) {
             rc = diagnostics(st, f, W_trace ? W_trace + seg + 1 : nullptr,

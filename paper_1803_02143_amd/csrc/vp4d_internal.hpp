@@ -117,6 +117,28 @@ __device__ __forceinline__ bool split_shift(double sigma, int n, int& s,
     return true;
 }
 
+// Reduce-scatter across groups of G lanes (G a power of two, V <= G <= 64):
+// on entry every lane holds v[0..V-1]; on return lane l holds the sum over
+// its group of the values with index l mod V (valid in lanes whose
+// l mod G < V).  V - 1 + log2(G/V) shuffles instead of V full reductions.
+template <int V, int G>
+__device__ __forceinline__ double group_reduce_scatter(double* v, int lane) {
+#pragma unroll
+    for (int m = V / 2; m >= 1; m >>= 1) {
+        const bool upper = (lane & m) != 0;
+#pragma unroll
+        for (int j = 0; j < m; ++j) {
+            const double keep = upper ? v[j + m] : v[j];
+            const double give = upper ? v[j] : v[j + m];
+            v[j] = keep + __shfl_xor(give, m, 64);
+        }
+    }
+    double r = v[0];
+#pragma unroll
+    for (int m = V; m < G; m <<= 1) r += __shfl_xor(r, m, 64);
+    return r;
+}
+
 // Launch geometry helpers.
 inline unsigned blocks_for(int64_t work, int per_block) {
     return static_cast<unsigned>((work + per_block - 1) / per_block);

@@ -283,3 +283,30 @@ def test_run_with_every_step_formed_is_the_plain_step():
     with pytest.raises(vp.VPError):
         st.run(b, tmp, 5, w.dt, 2)
     st.close()
+
+
+@pytest.mark.parametrize("method", ["sldg", "spline"])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_step_parity_with_density_from_the_x2_sweep(method, dt):
+    # N3 N4 = 256 velocity columns: the x2 sweep before each field solve
+    # also forms the density of its output (groups of 256 columns for SLDG,
+    # 64 for the spline); two steps against the oracle, W included
+    vp = require_gpu()
+    degree = 1 if method == "sldg" else None
+    dims = (12, 10, 16, 16)
+    w = workload("landau_8")
+    g = strang.Grid(dims, w.lo, w.length, degree)
+    f = field.initial_condition("landau", dims, w.lo, w.length, degree, w.eps, w.k)
+    st = vp.VPState(vp.METHOD_SLDG if method == "sldg" else vp.METHOD_SPLINE, 1,
+                    torch.float64 if dt == "f64" else torch.float32, dims, w.lo, w.length)
+    fd = to_dev(f, dt)
+    f_in = to_host(fd)
+    tmp = torch.empty_like(fd)
+    W = torch.empty(3, dtype=torch.float64, device="cuda")
+    announce(f"fused x2 density {method} {dt}")
+    st.step(fd, tmp, 2, w.dt, W)
+    ref, Wr = strang.run(f_in, g, w.dt, 2)
+    assert_close(to_host(fd), ref, dt, "two steps")
+    tol = 1e-12 if dt == "f64" else 1e-5
+    assert np.max(np.abs(to_host(W) - Wr) / Wr) <= tol
+    st.close()
