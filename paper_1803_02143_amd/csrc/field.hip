@@ -226,6 +226,33 @@ rho_from_parts(const double* __restrict__ part, int64_t groups, int64_t n2,
 
 constexpr int kFinalBlock = 1024;
 
+// out4 = (mass, L1, L2, kinetic) from per-workgroup sums of the fused x2
+// sweep: thread t adds parts t, t + 1024, ... in order, then a fixed-order
+// block reduction.
+__global__ void __launch_bounds__(kFinalBlock)
+moments_from_parts(const double* __restrict__ part, int64_t nparts, double* __restrict__ out4) {
+    __shared__ double red[4][kFinalBlock / 64];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t q = threadIdx.x; q < nparts; q += kFinalBlock)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] += part[4 * q + k];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double v = wave_sum64(acc[k]);
+        if (lane == 0) red[k][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+        for (int w = 0; w < kFinalBlock / 64; ++w) t += red[threadIdx.x][w];
+        if (threadIdx.x == 2) t = sqrt(t);
+        if (threadIdx.x == 3) t *= 0.5;
+        out4[threadIdx.x] = t;
+    }
+}
+
 // out4 = (mass, L1, L2, kinetic) from the per-(x1,x2) partial sums.
 __global__ void __launch_bounds__(kFinalBlock)
 moments_final(const double* __restrict__ part, int n1, int n2, AxisGrid g1,
@@ -357,6 +384,19 @@ vp_status launch_reduce(bool diag, const int64_t dims[4], const void* f,
 }
 
 }  // namespace
+
+vp_status moments_from_parts_impl(const double* mom_part, int64_t nparts, double* out4,
+                                  hipStream_t st) {
+    moments_from_parts<<<1, kFinalBlock, 0, st>>>(mom_part, nparts, out4);
+    return check_launch("moments_from_parts");
+}
+
+int64_t rho_fuse_workgroups(int method, vp_dtype dt, const int64_t dims[4]) {
+    const int64_t nvel = dims[2] * dims[3];
+    if (method == 0) return nvel % 256 == 0 ? dims[0] * nvel / 256 : 0;
+    const int gsz = spline_rho_group(dt, dims);
+    return gsz > 0 ? dims[0] * nvel / gsz : 0;
+}
 
 vp_status rho_from_parts_impl(const double* part, int64_t n1, int64_t groups, int64_t n2,
                               double* rho, hipStream_t st) {

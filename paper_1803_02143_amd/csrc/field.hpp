@@ -25,10 +25,15 @@ vp_status check_grid_args(int degree, vp_dtype dt, const int64_t dims[4],
 // group of adjacent velocity columns that a workgroup (or wavefront) owns
 // adds W3 W4 f_out over its columns into part[(x1 * groups + g) * N2 + j],
 // and rho_from_parts sums the groups in a fixed order.
+// With mom_part set, the sweep also adds up the moments of its output: each
+// workgroup writes its sums of W f, W |f|, W f^2 and W |v|^2 f (W the 4D
+// quadrature weight) to mom_part[4 * workgroup + q].
 struct RhoFuse {
-    double* part;    // device, x1 * groups * N2 doubles
-    AxisGrid g3, g4; // velocity node weights
-    int n4;          // N4 (v2 nodes), to split the column index
+    double* part;        // device, x1 * groups * N2 doubles
+    double* mom_part;    // device, 4 doubles per workgroup, or NULL
+    AxisGrid g1, g2;     // x node weights (moments)
+    AxisGrid g3, g4;     // velocity node weights and coordinates
+    int n4;              // N4 (v2 nodes), to split the column index
 };
 // Velocity columns per group of the fused spline x2 sweep (0: no fused
 // path for this grid); the SLDG one uses groups of 256 columns when N3 N4 is
@@ -44,6 +49,11 @@ vp_status spline_advect_rho_impl(vp_dtype dt, const int64_t dims[4], const void*
                                  hipStream_t st);
 vp_status rho_from_parts_impl(const double* part, int64_t n1, int64_t groups, int64_t n2,
                               double* rho, hipStream_t st);
+// out4 = (mass, L1, L2, kinetic energy) from nparts workgroup sums (4 each)
+vp_status moments_from_parts_impl(const double* mom_part, int64_t nparts, double* out4,
+                                  hipStream_t st);
+// workgroups of the fused x2 sweep (the number of mom_part entries / 4)
+int64_t rho_fuse_workgroups(int method, vp_dtype dt, const int64_t dims[4]);
 
 // Sweep (adjoint = false) or its transpose for fixed shifts (adjoint = true).
 vp_status sldg_advect_impl(int axis, int degree, vp_dtype dt,

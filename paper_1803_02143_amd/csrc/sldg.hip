@@ -275,7 +275,7 @@ sldg_col(const T* __restrict__ fin, T* __restrict__ fout,
 // the wavefront; the four wavefronts' sums meet in LDS, and each workgroup
 // writes the partial density of its 256 velocity columns (inner must be a
 // multiple of the workgroup size).  Every input cell is loaded once.
-template <int M, typename T>
+template <int M, typename T, bool MOM>
 __global__ void __launch_bounds__(kBlock)
 sldg_col_rho(const T* __restrict__ fin, T* __restrict__ fout,
              const double* __restrict__ shift, ShiftMap sm, int nc, int64_t inner,
@@ -307,6 +307,11 @@ sldg_col_rho(const T* __restrict__ fin, T* __restrict__ fout,
         prev[l] = first[l];
     }
     int rc = l0 + 1 == nc ? 0 : l0 + 1;   // next input cell to load
+    // moments: sums over this column of W2 f, W2 |f|, W2 f^2 (x2 weights)
+    double s_m = 0.0, s_a = 0.0, s_q = 0.0;
+    double w2[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) w2[j] = MOM ? rf.g2.w[j] * rf.g2.h : 0.0;
     constexpr int CU = M <= 3 ? 4 : 2;          // cells whose loads are in flight together
     constexpr int V = 2 * M <= 4 ? 4 : (2 * M <= 8 ? 8 : 16);   // two cells per reduction
     int i = 0;
@@ -334,7 +339,13 @@ sldg_col_rho(const T* __restrict__ fin, T* __restrict__ fout,
 #pragma unroll
                     for (int l = 0; l < M; ++l) acc = fma(B[j][l], cur[u][l], acc);
                     dst[(i + u) * cs + j * inner] = acc;
-                    vals[(u - h) * M + j] = wk * static_cast<double>(acc);
+                    const double ov = static_cast<double>(acc);
+                    vals[(u - h) * M + j] = wk * ov;
+                    if (MOM) {
+                        s_m = fma(w2[j], ov, s_m);
+                        s_a = fma(w2[j], fabs(ov), s_a);
+                        s_q = fma(w2[j] * ov, ov, s_q);
+                    }
                 }
 #pragma unroll
                 for (int l = 0; l < M; ++l) prev[l] = cur[u][l];
@@ -366,7 +377,13 @@ sldg_col_rho(const T* __restrict__ fin, T* __restrict__ fout,
 #pragma unroll
             for (int l = 0; l < M; ++l) acc = fma(B[j][l], cur[l], acc);
             dst[i * cs + j * inner] = acc;
-            vals[j] = wk * static_cast<double>(acc);
+            const double ov = static_cast<double>(acc);
+            vals[j] = wk * ov;
+            if (MOM) {
+                s_m = fma(w2[j], ov, s_m);
+                s_a = fma(w2[j], fabs(ov), s_a);
+                s_q = fma(w2[j] * ov, ov, s_q);
+            }
         }
         const double r = group_reduce_scatter<VT, 64>(vals, lane);
         if (lane < M) rp[wave * N + i * M + lane] = r;
@@ -374,12 +391,34 @@ sldg_col_rho(const T* __restrict__ fin, T* __restrict__ fout,
         for (int l = 0; l < M; ++l) prev[l] = cur[l];
         rc = rc + 1 == nc ? 0 : rc + 1;
     }
+    if (MOM) {
+        // W = W1 W2 W3 W4; |v|^2 is constant on a velocity column
+        const double w1 = rf.g1.w[o % rf.g1.m] * rf.g1.h;
+        const double a1 = rf.g3.lo + (static_cast<double>(v1 / rf.g3.m) + rf.g3.xi[v1 % rf.g3.m]) * rf.g3.h;
+        const double a2 = rf.g4.lo + (static_cast<double>(v2 / rf.g4.m) + rf.g4.xi[v2 % rf.g4.m]) * rf.g4.h;
+        const double f0 = w1 * wk;
+        double q[4] = {f0 * s_m, f0 * s_a, f0 * s_q, f0 * (a1 * a1 + a2 * a2) * s_m};
+        double* red = rp + (kBlock / 64) * N;   // [4][kBlock / 64]
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) q[t] += __shfl_xor(q[t], off, 64);
+            if (lane == 0) red[t * (kBlock / 64) + wave] = q[t];
+        }
+    }
     __syncthreads();
     for (int j = threadIdx.x; j < N; j += kBlock) {
         double t = 0.0;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; ++w) t += rp[w * N + j];
         rf.part[static_cast<int64_t>(blockIdx.x) * N + j] = t;
+    }
+    if (MOM && threadIdx.x < 4) {
+        const double* red = rp + (kBlock / 64) * N;
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) t += red[threadIdx.x * (kBlock / 64) + w];
+        rf.mom_part[static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x] = t;
     }
 }
 
@@ -527,11 +566,16 @@ vp_status launch_sldg_rho(const int64_t dims[4], const void* fin, void* fout,
     const int64_t outer = dims[0];
     const int64_t inner = dims[2] * dims[3];
     const int nc = static_cast<int>(dims[1] / M);
-    const size_t lds = sizeof(double) * (kBlock / 64) * static_cast<size_t>(dims[1]);
+    const size_t lds = sizeof(double) * (kBlock / 64) * (static_cast<size_t>(dims[1]) + 4);
     if (inner % kBlock || lds > 48 * 1024)
         return set_error(VP_ERR_UNSUPPORTED, "fused x2 sweep needs whole workgroups of columns");
-    sldg_col_rho<M, T><<<blocks_for(outer * inner, kBlock), kBlock, lds, st>>>(
-        static_cast<const T*>(fin), static_cast<T*>(fout), shift, sm, nc, inner, b, rf);
+    const unsigned grid = blocks_for(outer * inner, kBlock);
+    if (rf.mom_part)
+        sldg_col_rho<M, T, true><<<grid, kBlock, lds, st>>>(
+            static_cast<const T*>(fin), static_cast<T*>(fout), shift, sm, nc, inner, b, rf);
+    else
+        sldg_col_rho<M, T, false><<<grid, kBlock, lds, st>>>(
+            static_cast<const T*>(fin), static_cast<T*>(fout), shift, sm, nc, inner, b, rf);
     return check_launch("sldg_col_rho");
 }
 

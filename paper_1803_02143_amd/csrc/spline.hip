@@ -206,8 +206,9 @@ __device__ __forceinline__ int first_tap(int i, int s, int n) {
 }
 
 // kFwdRho: the forward sweep that also writes the partial density of its
-// output (x2 sweeps with 64-line tiles; the workgroup's 64 columns)
-enum { kFwd = 0, kAdj = 1, kDshift = 2, kFwdRho = 3 };
+// output (x2 sweeps with 64-line tiles; the workgroup's 64 columns);
+// kFwdRhoMom: and the workgroup's sums of the four moments of its output
+enum { kFwd = 0, kAdj = 1, kDshift = 2, kFwdRho = 3, kFwdRhoMom = 4 };
 
 // Longest segment a thread owns: tiles hold at most kTileBytes, so a
 // segment has at most kTileBytes / (kBlock * sizeof(T)) points.
@@ -286,7 +287,11 @@ __global__ void __launch_bounds__(kBlock)
 spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ lam,
            double* __restrict__ g, const double* __restrict__ shift, ShiftMap sm,
            int64_t nlines, int64_t inner, int L, SplineParams<T> sp, RhoFuse rf) {
-    constexpr bool FWD = MODE == kFwd || MODE == kFwdRho;
+    constexpr bool RHO = MODE == kFwdRho || MODE == kFwdRhoMom;
+    constexpr bool MOM = MODE == kFwdRhoMom;
+    constexpr bool FWD = MODE == kFwd || RHO;
+    __shared__ double mred[MOM ? 4 * (kBlock / 64) : 1];
+    double s_m = 0.0, s_a = 0.0, s_q = 0.0;   // W2 f, W2 |f|, W2 f^2 of this line
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[MODE == kDshift ? kBlock : 1];
     const int n = sp.n;
@@ -383,9 +388,9 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         j = next_idx(j, n);
         T c3 = buf[j * L + l];
         int i = b;
-        // density weight of this line's velocity column (kFwdRho)
+        // density weight of this line's velocity column
         double wk = 0.0;
-        if (MODE == kFwdRho) {
+        if (RHO) {
             const int v1 = static_cast<int>(kl / rf.n4);
             const int v2 = static_cast<int>(kl - static_cast<int64_t>(v1) * rf.n4);
             wk = rf.g3.w[v1 % rf.g3.m] * rf.g3.h * (rf.g4.w[v2 % rf.g4.m] * rf.g4.h);
@@ -404,10 +409,21 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                 dst[static_cast<int64_t>(i + 1) * inner] = o1;
                 dst[static_cast<int64_t>(i + 2) * inner] = o2;
                 dst[static_cast<int64_t>(i + 3) * inner] = o3;
-                if (MODE == kFwdRho) {
+                if (RHO) {
                     // the wavefront's 64 lines share i: sums over them
                     double vals[4] = {wk * static_cast<double>(o0), wk * static_cast<double>(o1),
                                       wk * static_cast<double>(o2), wk * static_cast<double>(o3)};
+                    if (MOM) {
+                        const double w2 = rf.g2.h;
+                        const double ov[4] = {static_cast<double>(o0), static_cast<double>(o1),
+                                              static_cast<double>(o2), static_cast<double>(o3)};
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            s_m = fma(w2, ov[q], s_m);
+                            s_a = fma(w2, fabs(ov[q]), s_a);
+                            s_q = fma(w2 * ov[q], ov[q], s_q);
+                        }
+                    }
                     const double r = group_reduce_scatter<4, 64>(vals, threadIdx.x & 63);
                     if ((threadIdx.x & 63) < 4)
                         rf.part[static_cast<int64_t>(blockIdx.x) * n + i + (threadIdx.x & 63)] = r;
@@ -423,8 +439,14 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
             for (; i < e; ++i) {
                 const T o = fma(w3, c3, fma(w2, c2, fma(w1, c1, w0 * c0)));
                 dst[static_cast<int64_t>(i) * inner] = o;
-                if (MODE == kFwdRho) {
+                if (RHO) {
                     double vals[1] = {wk * static_cast<double>(o)};
+                    if (MOM) {
+                        const double ov = static_cast<double>(o);
+                        s_m = fma(rf.g2.h, ov, s_m);
+                        s_a = fma(rf.g2.h, fabs(ov), s_a);
+                        s_q = fma(rf.g2.h * ov, ov, s_q);
+                    }
                     const double r = group_reduce_scatter<1, 64>(vals, threadIdx.x & 63);
                     if ((threadIdx.x & 63) == 0) rf.part[static_cast<int64_t>(blockIdx.x) * n + i] = r;
                 }
@@ -456,6 +478,32 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
             double t = 0.0;
             for (int q = 0; q < Q; ++q) t += red[q * L + threadIdx.x];
             g[line0 + threadIdx.x] = t;
+        }
+    }
+    if (MOM) {
+        // workgroup sums of W f, W |f|, W f^2, W |v|^2 f (|v|^2 constant on
+        // a line); every thread of the tile is active on this path
+        const int v1 = static_cast<int>(kl / rf.n4);
+        const int v2 = static_cast<int>(kl - static_cast<int64_t>(v1) * rf.n4);
+        const double a1 = rf.g3.lo + (static_cast<double>(v1) + rf.g3.xi[0]) * rf.g3.h;
+        const double a2 = rf.g4.lo + (static_cast<double>(v2) + rf.g4.xi[0]) * rf.g4.h;
+        const double wv = rf.g3.h * rf.g4.h;
+        const double f0 = rf.g1.h * wv;
+        double q[4] = {f0 * s_m, f0 * s_a, f0 * s_q, f0 * (a1 * a1 + a2 * a2) * s_m};
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) q[t] += __shfl_xor(q[t], off, 64);
+            if (lane == 0) mred[t * (kBlock / 64) + wave] = q[t];
+        }
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) t += mred[threadIdx.x * (kBlock / 64) + w];
+            rf.mom_part[static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x] = t;
         }
     }
 }
@@ -665,7 +713,7 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
         // tiles run over the flattened line index
         const int L = tile_lines(n, sizeof(T));
         const size_t lds = static_cast<size_t>(n) * L * sizeof(T);
-        if (MODE == kFwdRho && (axis != 1 || L != 64 || inner % 64))
+        if ((MODE == kFwdRho || MODE == kFwdRhoMom) && (axis != 1 || L != 64 || inner % 64))
             return set_error(VP_ERR_UNSUPPORTED, "fused x2 sweep needs 64-line tiles");
         if (lds > kTileBytes)
             return set_error(VP_ERR_UNSUPPORTED,
@@ -675,7 +723,7 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
         if (grid64 >= (int64_t(1) << 31))
             return set_error(VP_ERR_UNSUPPORTED, "spline_advect: grid too large");
         const unsigned grid = static_cast<unsigned>(grid64);
-        if constexpr (MODE == kFwdRho) {
+        if constexpr (MODE == kFwdRho || MODE == kFwdRhoMom) {
             spline_col<T, 1, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
         } else {
             switch (axis) {
@@ -692,7 +740,7 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
         }
         return check_launch("spline_col");
     }
-    if constexpr (MODE == kFwdRho) {
+    if constexpr (MODE == kFwdRho || MODE == kFwdRhoMom) {
         return set_error(VP_ERR_UNSUPPORTED, "fused density only on x2 sweeps");
     } else {
     // rows per tile: a power of two (so every segment fits SegMax) within
@@ -732,10 +780,16 @@ vp_status spline_advect_rho_impl(vp_dtype dt, const int64_t dims[4], const void*
                                  hipStream_t st) {
     const ShiftMap sm = make_shift_map(1, dims, shift_stride);
     if (dt == VP_F64)
-        return launch_spline<double, kFwdRho>(1, dims, f_in, f_out, nullptr, nullptr, shift, sm,
-                                              st, rf);
-    return launch_spline<float, kFwdRho>(1, dims, f_in, f_out, nullptr, nullptr, shift, sm, st,
-                                         rf);
+        return rf.mom_part
+                   ? launch_spline<double, kFwdRhoMom>(1, dims, f_in, f_out, nullptr, nullptr,
+                                                       shift, sm, st, rf)
+                   : launch_spline<double, kFwdRho>(1, dims, f_in, f_out, nullptr, nullptr,
+                                                    shift, sm, st, rf);
+    return rf.mom_part
+               ? launch_spline<float, kFwdRhoMom>(1, dims, f_in, f_out, nullptr, nullptr, shift,
+                                                  sm, st, rf)
+               : launch_spline<float, kFwdRho>(1, dims, f_in, f_out, nullptr, nullptr, shift, sm,
+                                               st, rf);
 }
 
 int spline_rho_group(vp_dtype dt, const int64_t dims[4]) {

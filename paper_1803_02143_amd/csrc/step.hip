@@ -28,6 +28,8 @@ struct vp_state {
     double *sig_x1f, *sig_x2f;  // x shifts of a whole step (merged half-steps)
     double* rho_part;           // partial densities of the fused x2 sweep
     int64_t rho_groups;         // column groups per x1 (0: no fused x2 sweep)
+    double* mom_part;           // its per-workgroup moment sums (4 each)
+    int64_t mom_parts;          // workgroups of the fused x2 sweep
     double* partial;  // 4 * n1 * n2
     double *gs1, *gs2, *rho_bar;  // adjoint: shift gradients and transposed density
     void* pws;        // Poisson workspace
@@ -96,13 +98,16 @@ vp_status sweep(vp_state* st, int axis, const void* in, void* out,
 // it, the sweep also writes the partial densities of its output (and the
 // field then sums them instead of reading the state again).
 vp_status sweep_x2_rho(vp_state* st, const void* in, void* out, const double* shift,
-                       hipStream_t s, bool& fused) {
+                       hipStream_t s, bool& fused, bool moments = false) {
     fused = st->rho_groups > 0;
     if (!fused) return sweep(st, 1, in, out, shift, s);
     int64_t stride[4];
     step_strides(st, 1, stride);
     RhoFuse rf{};
     rf.part = st->rho_part;
+    rf.mom_part = moments ? st->mom_part : nullptr;
+    rf.g1 = axis_grid(st->degree, st->dims[0], st->lo[0], st->len[0]);
+    rf.g2 = axis_grid(st->degree, st->dims[1], st->lo[1], st->len[1]);
     rf.g3 = axis_grid(st->degree, st->dims[2], st->lo[2], st->len[2]);
     rf.g4 = axis_grid(st->degree, st->dims[3], st->lo[3], st->len[3]);
     rf.n4 = static_cast<int>(st->dims[3]);
@@ -112,6 +117,22 @@ vp_status sweep_x2_rho(vp_state* st, const void* in, void* out, const double* sh
                                               stride, rf, s)
                        : spline_advect_rho_impl(st->dt, st->dims, in, out, shift, stride, rf, s);
     mark(st, VP_TIMER_SWEEP_X2_RHO, s);
+    return rc;
+}
+
+// W (and the moments) of the state just written by a fused x2 sweep, from
+// its partial sums.
+vp_status diagnostics_fused(vp_state* st, double* W, double* mom, hipStream_t s) {
+    mark(st, VP_TIMER_DIAG, s);
+    vp_status rc = VP_OK;
+    if (mom) rc = moments_from_parts_impl(st->mom_part, st->mom_parts, mom, s);
+    if (rc == VP_OK && W)
+        rc = rho_from_parts_impl(st->rho_part, st->dims[0], st->rho_groups, st->dims[1],
+                                 st->rho, s);
+    if (rc == VP_OK && W)
+        rc = poisson_impl(st->degree, st->dims[0], st->dims[1], st->len[0], st->len[1],
+                          st->rho, st->e1, st->e2, W, st->pws, s);
+    mark(st, VP_TIMER_DIAG, s);
     return rc;
 }
 
@@ -212,9 +233,10 @@ extern "C" vp_status vp_create(vp_state** out, int method, int degree, vp_dtype 
     if (method == 0 && nvel % 256 == 0) groups = nvel / 256;
     if (method == 1 && spline_rho_group(dt, dims) > 0) groups = nvel / spline_rho_group(dt, dims);
     const size_t npart = static_cast<size_t>(dims[0] * groups * dims[1]);
+    const int64_t nwg = groups > 0 ? rho_fuse_workgroups(method, dt, dims) : 0;
     const size_t ndbl = static_cast<size_t>(nx) * (5 + 4 + 3) +
                         3 * static_cast<size_t>(dims[2] + dims[3]) + pws / sizeof(double) + 64 +
-                        npart + 32;
+                        npart + 4 * static_cast<size_t>(nwg) + 32;
     void* mem = nullptr;
     hipError_t e = hipMalloc(&mem, ndbl * sizeof(double));
     if (e != hipSuccess) {
@@ -242,6 +264,9 @@ extern "C" vp_status vp_create(vp_state** out, int method, int degree, vp_dtype 
     st->rho_groups = groups;
     st->rho_part = p;
     p += npart;
+    st->mom_parts = nwg;
+    st->mom_part = p;
+    p += 4 * nwg;
     p = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(p) + 255) & ~uintptr_t(255));
     st->pws = p;
     // velocity node coordinates, used for the x-sweep shifts
@@ -326,15 +351,20 @@ vp_status strang_run(vp_state* st, void* f, void* f_tmp, int nsteps, double tau,
             const bool last = j == every - 1;
             if ((rc = sweep(st, 0, f, f_tmp, last ? st->sig_x1 : st->sig_x1f, s)) != VP_OK)
                 return rc;
-            if (last)
-                rc = sweep(st, 1, f_tmp, f, st->sig_x2, s);
-            else
+            if (!last)
                 rc = sweep_x2_rho(st, f_tmp, f, st->sig_x2f, s, fused);
+            else if (diag)
+                // the state of the diagnostics: its density and moments
+                // come with the closing sweep
+                rc = sweep_x2_rho(st, f_tmp, f, st->sig_x2, s, fused, moments != nullptr);
+            else
+                rc = sweep(st, 1, f_tmp, f, st->sig_x2, s);
             if (rc != VP_OK) return rc;
         }
         if (diag) {
-            rc = diagnostics(st, f, W_trace ? W_trace + seg + 1 : nullptr,
-                             moments ? moments + 4 * (seg + 1) : nullptr, s);
+            double* Wd = W_trace ? W_trace + seg + 1 : nullptr;
+            double* md = moments ? moments + 4 * (seg + 1) : nullptr;
+            rc = fused ? diagnostics_fused(st, Wd, md, s) : diagnostics(st, f, Wd, md, s);
             if (rc != VP_OK) return rc;
         }
     }

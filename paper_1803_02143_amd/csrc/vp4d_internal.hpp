@@ -117,6 +117,38 @@ __device__ __forceinline__ bool split_shift(double sigma, int n, int& s,
     return true;
 }
 
+// v from lane (lane ^ m), m a power of two known at compile time after
+// unrolling: within a quad by DPP quad permutations, up to 16 by the
+// swizzle crossbar (bit mode: and 0x1F, xor m), 32 by a lane permute.
+__device__ __forceinline__ double xor_lanes(double v, int m) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    switch (m) {
+        case 1:
+            lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+            hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
+            break;
+        case 2:
+            lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+            hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false);
+            break;
+        case 4:
+            lo = __builtin_amdgcn_ds_swizzle(lo, 0x1F | (4 << 10));
+            hi = __builtin_amdgcn_ds_swizzle(hi, 0x1F | (4 << 10));
+            break;
+        case 8:
+            lo = __builtin_amdgcn_ds_swizzle(lo, 0x1F | (8 << 10));
+            hi = __builtin_amdgcn_ds_swizzle(hi, 0x1F | (8 << 10));
+            break;
+        case 16:
+            lo = __builtin_amdgcn_ds_swizzle(lo, 0x1F | (16 << 10));
+            hi = __builtin_amdgcn_ds_swizzle(hi, 0x1F | (16 << 10));
+            break;
+        default:
+            return __shfl_xor(v, m, 64);
+    }
+    return __hiloint2double(hi, lo);
+}
+
 // Reduce-scatter across groups of G lanes (G a power of two, V <= G <= 64):
 // on entry every lane holds v[0..V-1]; on return lane l holds the sum over
 // its group of the values with index l mod V (valid in lanes whose
@@ -130,12 +162,12 @@ __device__ __forceinline__ double group_reduce_scatter(double* v, int lane) {
         for (int j = 0; j < m; ++j) {
             const double keep = upper ? v[j + m] : v[j];
             const double give = upper ? v[j] : v[j + m];
-            v[j] = keep + __shfl_xor(give, m, 64);
+            v[j] = keep + xor_lanes(give, m);
         }
     }
     double r = v[0];
 #pragma unroll
-    for (int m = V; m < G; m <<= 1) r += __shfl_xor(r, m, 64);
+    for (int m = V; m < G; m <<= 1) r += xor_lanes(r, m);
     return r;
 }
 

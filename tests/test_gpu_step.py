@@ -303,10 +303,18 @@ def test_step_parity_with_density_from_the_x2_sweep(method, dt):
     f_in = to_host(fd)
     tmp = torch.empty_like(fd)
     W = torch.empty(3, dtype=torch.float64, device="cuda")
+    mom = torch.empty(12, dtype=torch.float64, device="cuda")
     announce(f"fused x2 density {method} {dt}")
-    st.step(fd, tmp, 2, w.dt, W)
-    ref, Wr = strang.run(f_in, g, w.dt, 2)
+    st.step(fd, tmp, 2, w.dt, W, mom)
+    ref, Wr, mr = strang.run(f_in, g, w.dt, 2, with_moments=True)
     assert_close(to_host(fd), ref, dt, "two steps")
     tol = 1e-12 if dt == "f64" else 1e-5
     assert np.max(np.abs(to_host(W) - Wr) / Wr) <= tol
+    np.testing.assert_allclose(to_host(mom).reshape(3, 4), mr, rtol=tol)
+    # the same steps with W only (density without the moment sums)
+    fd2 = to_dev(f_in, dt)
+    W2 = torch.empty(3, dtype=torch.float64, device="cuda")
+    st.step(fd2, tmp, 2, w.dt, W2)
+    assert torch.equal(fd2, fd)
+    assert np.max(np.abs(to_host(W2) - Wr) / Wr) <= tol
     st.close()
