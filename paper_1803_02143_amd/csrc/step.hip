@@ -482,9 +482,10 @@ extern "C" vp_status vp_strang_adjoint(vp_state* st, const void* f, void* lam, d
     if ((rc = sweep(st, 1, lam, bufQ, st->sig_x2, s, true)) != VP_OK) return rc;
     if ((rc = sweep(st, 0, bufQ, lam, st->sig_x1, s, true)) != VP_OK) return rc;
     // recompute the states the shift derivatives need: f2 (P), f3 (Q)
+    bool fused = false;
     if ((rc = sweep(st, 0, f, bufQ, st->sig_x1, s)) != VP_OK) return rc;
-    if ((rc = sweep(st, 1, bufQ, bufP, st->sig_x2, s)) != VP_OK) return rc;
-    rc = density_impl(st->degree, st->dt, st->dims, bufP, st->len[2], st->len[3], st->rho, s);
+    if ((rc = sweep_x2_rho(st, bufQ, bufP, st->sig_x2, s, fused)) != VP_OK) return rc;
+    rc = density_of(st, bufP, fused, s);
     if (rc == VP_OK)
         rc = poisson_impl_shift(st->degree, st->dims[0], st->dims[1], st->len[0], st->len[1],
                                 st->rho, st->e1, st->e2, nullptr, st->pws, st->sig_v1,

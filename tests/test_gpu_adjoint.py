@@ -72,8 +72,10 @@ def test_density_and_poisson_adjoint(degree):
 
 
 def _small(method):
+    # 16 x 16 velocity nodes: the x2 sweep before the field solve also forms
+    # the density (256 columns per SLDG workgroup, 64-line spline tiles)
     degree = 1 if method == "sldg" else None
-    dims = (8, 8, 12, 12)
+    dims = (8, 8, 16, 16)
     return strang.Grid(dims, (0.0, 0.0, -6.0, -6.0), (4 * math.pi, 4 * math.pi, 12.0, 12.0),
                        degree)
 
