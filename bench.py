@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the timing of the adjoint step and its kernels")
     ap.add_argument("--adjoint-steps", type=int, default=20)
+    ap.add_argument("--no-microbench", action="store_true",
+                    help="skip the isolated per-axis sweep timings")
     ap.add_argument("--no-merged", action="store_true",
                     help="skip the timing of runs with merged x half-steps")
     ap.add_argument("--diag-every", type=int, default=10)
@@ -176,6 +178,65 @@ def _event_ms(torch, stream, fn, reps):
     b.record(stream)
     b.synchronize()
     return a.elapsed_time(b) / reps
+
+
+def sweep_microbench(vp, torch, w, methods, stream, reps=20, warmup=3):
+    """Every sweep on its own: per method, storage precision and axis, the
+    median of `reps` launches (after `warmup`) with the shifts of the first
+    step, a 512 MB read between launches so that no launch finds its data
+    (or dirty lines of the previous launch) in the caches; and the rate of a
+    plain device copy of one f buffer measured the same way (the practical
+    streaming ceiling)."""
+    import numpy as np
+
+    dims = w.dofs
+    n4 = int(np.prod(dims))
+    flush = torch.ones(512 * 2 ** 20 // 4, dtype=torch.float32, device="cuda")
+    out = {}
+
+    def timed(fn):
+        ts = []
+        for r in range(warmup + reps):
+            flush.sum()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            b.synchronize()
+            if r >= warmup:
+                ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    for dt, tdt, es in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+        f = torch.empty(dims, dtype=tdt, device="cuda")
+        g = torch.empty_like(f)
+        f.uniform_()
+        ms = timed(lambda: g.copy_(f))
+        res = {"copy": {"ms": ms, "GBs": 2 * n4 * es / (ms * 1e-3) / 1e9}}
+        copy_gbs = res["copy"]["GBs"]
+        for m in methods:
+            deg = w.degree if m == "sldg" else -1
+            shifts = step_shifts(w, deg)
+            per = {}
+            for axis in range(4):
+                sig = torch.from_numpy(shifts[axis]).cuda()
+                if m == "sldg":
+                    fn = lambda: vp.sldg_advect(axis, w.degree, f, g, sig, stream=stream)
+                else:
+                    fn = lambda: vp.spline_advect(axis, f, g, sig, stream=stream)
+                ms = timed(fn)
+                gbs = 2 * n4 * es / (ms * 1e-3) / 1e9
+                per[("x1", "x2", "v1", "v2")[axis]] = {
+                    "us": ms * 1e3, "dof_updates_per_s": n4 / (ms * 1e-3), "alg_GBs": gbs,
+                    "frac_of_peak": gbs / HBM_PEAK_GBS, "frac_of_copy": gbs / copy_gbs}
+            per["mean_frac_of_peak"] = float(np.mean([v["frac_of_peak"] for v in per.values()]))
+            res[m] = per
+        out[dt] = res
+        del f, g
+    del flush
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_merged(vp, torch, w, dt, methods, steps, every, stream):
@@ -375,6 +436,9 @@ def main():
         "W_el_last": W_last,
         "rel_mass_drift": mass_drift,
     }
+
+    if not a.no_microbench:
+        out["sweep_microbench"] = sweep_microbench(vp, torch, w, methods, stream)
 
     if not a.no_merged:
         mr = run_merged(vp, torch, w, dt, methods, a.steps, a.diag_every, stream)
