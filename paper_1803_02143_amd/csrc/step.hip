@@ -230,7 +230,10 @@ extern "C" vp_status vp_create(vp_state** out, int method, int degree, vp_dtype 
     // columns: 256 per workgroup for SLDG, 64 per tile for the spline
     const int64_t nvel = dims[2] * dims[3];
     int64_t groups = 0;
-    if (method == 0 && nvel % 256 == 0) groups = nvel / 256;
+    // (SLDG: whole workgroups of 256 columns, and the four wavefronts' N2
+    // partial sums in 48 KiB of LDS)
+    if (method == 0 && nvel % 256 == 0 && 4 * (dims[1] + 4) * 8 <= 48 * 1024)
+        groups = nvel / 256;
     if (method == 1 && spline_rho_group(dt, dims) > 0) groups = nvel / spline_rho_group(dt, dims);
     const size_t npart = static_cast<size_t>(dims[0] * groups * dims[1]);
     const int64_t nwg = groups > 0 ? rho_fuse_workgroups(method, dt, dims) : 0;
