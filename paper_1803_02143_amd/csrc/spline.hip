@@ -206,7 +206,7 @@ __device__ __forceinline__ int first_tap(int i, int s, int n) {
 }
 
 // kFwdRho: the forward sweep that also writes the partial density of its
-// output (x2 sweeps with 64-line tiles; the workgroup's 64 columns);
+// output (x2 sweeps with 32- or 64-line tiles; the workgroup's columns);
 // kFwdRhoMom: and the workgroup's sums of the four moments of its output
 enum { kFwd = 0, kAdj = 1, kDshift = 2, kFwdRho = 3, kFwdRhoMom = 4 };
 
@@ -424,9 +424,12 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                             s_q = fma(w2 * ov[q], ov[q], s_q);
                         }
                     }
-                    const double r = group_reduce_scatter<4, 64>(vals, threadIdx.x & 63);
-                    if ((threadIdx.x & 63) < 4)
-                        rf.part[static_cast<int64_t>(blockIdx.x) * n + i + (threadIdx.x & 63)] = r;
+                    // lanes of one segment: the whole wavefront (64-line
+                    // tiles) or its halves (32-line tiles, two segments)
+                    const int gl = threadIdx.x & (L - 1);
+                    const double r = L == 64 ? group_reduce_scatter<4, 64>(vals, threadIdx.x & 63)
+                                             : group_reduce_scatter<4, 32>(vals, threadIdx.x & 63);
+                    if (gl < 4) rf.part[static_cast<int64_t>(blockIdx.x) * n + i + gl] = r;
                 }
                 c0 = c4;
                 c1 = c5;
@@ -447,8 +450,10 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                         s_a = fma(rf.g2.h, fabs(ov), s_a);
                         s_q = fma(rf.g2.h * ov, ov, s_q);
                     }
-                    const double r = group_reduce_scatter<1, 64>(vals, threadIdx.x & 63);
-                    if ((threadIdx.x & 63) == 0) rf.part[static_cast<int64_t>(blockIdx.x) * n + i] = r;
+                    const double r = L == 64 ? group_reduce_scatter<1, 64>(vals, threadIdx.x & 63)
+                                             : group_reduce_scatter<1, 32>(vals, threadIdx.x & 63);
+                    if ((threadIdx.x & (L - 1)) == 0)
+                        rf.part[static_cast<int64_t>(blockIdx.x) * n + i] = r;
                 }
                 c0 = c1;
                 c1 = c2;
@@ -713,8 +718,10 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
         // tiles run over the flattened line index
         const int L = tile_lines(n, sizeof(T));
         const size_t lds = static_cast<size_t>(n) * L * sizeof(T);
-        if ((MODE == kFwdRho || MODE == kFwdRhoMom) && (axis != 1 || L != 64 || inner % 64))
-            return set_error(VP_ERR_UNSUPPORTED, "fused x2 sweep needs 64-line tiles");
+        if ((MODE == kFwdRho || MODE == kFwdRhoMom) &&
+            (axis != 1 || (L != 64 && L != 32) || inner % L || n % (kBlock / L)))
+            return set_error(VP_ERR_UNSUPPORTED,
+                             "fused x2 sweep needs 32- or 64-line tiles of equal segments");
         if (lds > kTileBytes)
             return set_error(VP_ERR_UNSUPPORTED,
                              "spline_advect: line of %d points too long for the LDS tile", n);
@@ -793,8 +800,12 @@ vp_status spline_advect_rho_impl(vp_dtype dt, const int64_t dims[4], const void*
 }
 
 int spline_rho_group(vp_dtype dt, const int64_t dims[4]) {
+    // the lanes of a segment must run the same evaluation steps: tiles of 64
+    // lines (one segment per wavefront) or 32 (two), segments of equal length
     const int L = tile_lines(static_cast<int>(dims[1]), dtype_size(dt));
-    return L == 64 && (dims[2] * dims[3]) % 64 == 0 ? 64 : 0;
+    if (L != 64 && L != 32) return 0;
+    if ((dims[2] * dims[3]) % L || dims[1] % (kBlock / L)) return 0;
+    return L;
 }
 
 vp_status spline_dshift_impl(int axis, vp_dtype dt, const int64_t dims[4], const void* f_in,

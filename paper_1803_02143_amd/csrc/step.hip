@@ -235,6 +235,9 @@ extern "C" vp_status vp_create(vp_state** out, int method, int degree, vp_dtype 
     if (method == 0 && nvel % 256 == 0 && 4 * (dims[1] + 4) * 8 <= 48 * 1024)
         groups = nvel / 256;
     if (method == 1 && spline_rho_group(dt, dims) > 0) groups = nvel / spline_rho_group(dt, dims);
+    // (not worth more than a sixteenth of a state in partial sums)
+    const size_t fbytes = static_cast<size_t>(total) * dtype_size(dt);
+    if (static_cast<size_t>(dims[0] * groups * dims[1]) * sizeof(double) > fbytes / 16) groups = 0;
     const size_t npart = static_cast<size_t>(dims[0] * groups * dims[1]);
     const int64_t nwg = groups > 0 ? rho_fuse_workgroups(method, dt, dims) : 0;
     const size_t ndbl = static_cast<size_t>(nx) * (5 + 4 + 3) +

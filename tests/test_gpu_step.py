@@ -285,15 +285,19 @@ def test_run_with_every_step_formed_is_the_plain_step():
     st.close()
 
 
-@pytest.mark.parametrize("method", ["sldg", "spline"])
-@pytest.mark.parametrize("dt", ["f64", "f32"])
-def test_step_parity_with_density_from_the_x2_sweep(method, dt):
-    # N3 N4 = 256 velocity columns: the x2 sweep before each field solve
-    # also forms the density of its output (groups of 256 columns for SLDG,
-    # 64 for the spline); two steps against the oracle, W included
+@pytest.mark.parametrize("method,dt,dims", [
+    ("sldg", "f64", (12, 10, 16, 16)), ("sldg", "f32", (12, 10, 16, 16)),
+    ("spline", "f64", (12, 10, 16, 16)), ("spline", "f32", (12, 10, 16, 16)),
+    ("spline", "f64", (6, 104, 16, 16)),     # 32-line tiles: two segments per wavefront
+    ("spline", "f32", (4, 200, 8, 16)),
+])
+def test_step_parity_with_density_from_the_x2_sweep(method, dt, dims):
+    # the x2 sweep before each field solve also forms the density of its
+    # output (groups of 256 velocity columns for SLDG, of 64 or 32 for the
+    # spline) and, before the diagnostics, the moments; two steps against
+    # the oracle, W and the moments included
     vp = require_gpu()
     degree = 1 if method == "sldg" else None
-    dims = (12, 10, 16, 16)
     w = workload("landau_8")
     g = strang.Grid(dims, w.lo, w.length, degree)
     f = field.initial_condition("landau", dims, w.lo, w.length, degree, w.eps, w.k)
