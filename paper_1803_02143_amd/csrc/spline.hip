@@ -535,7 +535,7 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     const int wave = threadIdx.x >> 6;
     constexpr int kWaves = kBlock / 64;
     // the tile's rows are contiguous in memory: flat element e = r*n + i,
-    // (r, i) advanced by kBlock elements per round; kU loads in flight with
+    // (r, i) advanced by kBlock elements per round; kUR loads in flight with
     // clamped indices, only the LDS stores guarded
     const int cnt = nr * n;
     const int dr = kBlock / n;
@@ -544,11 +544,12 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         const T* __restrict__ src = fin + row0 * n;
         int r = static_cast<int>(threadIdx.x) / n;
         int i = static_cast<int>(threadIdx.x) - r * n;
-        for (int e0 = threadIdx.x; e0 < cnt; e0 += kU * kBlock) {
-            T v[kU];
-            int pos[kU];
+        constexpr int kUR = 12;   // one batch per FP64 tile, two per FP32 tile
+        for (int e0 = threadIdx.x; e0 < cnt; e0 += kUR * kBlock) {
+            T v[kUR];
+            int pos[kUR];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
+            for (int u = 0; u < kUR; ++u) {
                 const int e = e0 + u * kBlock;
                 v[u] = src[e < cnt ? e : cnt - 1];
                 pos[u] = r * ld + i;
@@ -560,7 +561,7 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                 }
             }
 #pragma unroll
-            for (int u = 0; u < kU; ++u)
+            for (int u = 0; u < kUR; ++u)
                 if (e0 + u * kBlock < cnt) buf[pos[u]] = v[u];
         }
     }
