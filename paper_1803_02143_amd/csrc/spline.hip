@@ -329,14 +329,16 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                     if (i0 + u < e) buf[(i0 + u) * L + l] = v[u];
             }
         } else {
-            // FP32: batches of kU loads (registers limit the occupancy here)
+            // FP32: batches of 12 loads (registers, not the tile, limit the
+            // occupancy here)
+            constexpr int kV = 12;
             int i = b;
-            for (; i + kU <= e; i += kU) {
-                T v[kU];
+            for (; i + kV <= e; i += kV) {
+                T v[kV];
 #pragma unroll
-                for (int u = 0; u < kU; ++u) v[u] = src[static_cast<int64_t>(i + u) * inner];
+                for (int u = 0; u < kV; ++u) v[u] = src[static_cast<int64_t>(i + u) * inner];
 #pragma unroll
-                for (int u = 0; u < kU; ++u) buf[(i + u) * L + l] = v[u];
+                for (int u = 0; u < kV; ++u) buf[(i + u) * L + l] = v[u];
             }
             for (; i < e; ++i) buf[i * L + l] = src[static_cast<int64_t>(i) * inner];
         }
