@@ -166,10 +166,13 @@ VP4D_API vp_status vp_init(int kind, double eps, double k, double v0, int degree
                   const double len[4], void* f, void* stream);
 
 /*
- * vp_state -- a solver instance that owns only its two-dimensional scratch
- * (density, field, shift arrays, Poisson and moment workspaces) on the HIP
- * device current at vp_create.  Not thread safe; calls that share a state
- * must be serialised by the caller.
+ * vp_state -- a solver instance that owns its scratch on the HIP device
+ * current at vp_create: the two-dimensional arrays (density, field, shift
+ * arrays, Poisson and moment workspaces) and, where the x2 sweep forms the
+ * density of its output (see vp_strang_step), that sweep's partial sums:
+ * N1 N2 N3 N4 / 256 doubles for SLDG, N1 N2 N3 N4 / 64 or / 32 for the spline
+ * (at most 1/16 of the bytes of f).  f itself is always the caller's.  Not
+ * thread safe; calls that share a state must be serialised by the caller.
  *
  * vp_create   method 0 = SLDG (degree 0..VP_MAX_DEGREE), 1 = cubic spline
  *             (degree ignored).  dims/lo/len as above (host).
