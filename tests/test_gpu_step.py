@@ -322,3 +322,25 @@ def test_step_parity_with_density_from_the_x2_sweep(method, dt, dims):
     assert torch.equal(fd2, fd)
     assert np.max(np.abs(to_host(W2) - Wr) / Wr) <= tol
     st.close()
+
+
+def test_merged_run_parity_table1_64():
+    # dG4 at 64^4 (the x2 sweeps form the density and moments of their
+    # output): two steps merged into one segment against the oracle
+    vp = require_gpu()
+    w = workload("landau_table1_64")
+    g = _grid(w, "sldg")
+    announce("merged run dG4 64^4: oracle")
+    f0 = field.initial_condition("landau", w.dofs, w.lo, w.length, w.degree, w.eps, w.k)
+    ref, Wr, mr = strang.run_merged(f0, g, w.dt, 2, 2, with_moments=True)
+    st = vp.VPState(vp.METHOD_SLDG, w.degree, torch.float64, w.dofs, w.lo, w.length)
+    fd = to_dev(f0)
+    tmp = torch.empty_like(fd)
+    W = torch.empty(2, dtype=torch.float64, device="cuda")
+    mom = torch.empty(8, dtype=torch.float64, device="cuda")
+    announce("merged run dG4 64^4: device")
+    st.run(fd, tmp, 2, w.dt, 2, W, mom)
+    assert_close(to_host(fd), ref, "f64", "merged 64^4")
+    assert np.max(np.abs(to_host(W) - Wr) / Wr) <= 1e-12
+    np.testing.assert_allclose(to_host(mom).reshape(2, 4), mr, rtol=1e-12)
+    st.close()
