@@ -292,6 +292,12 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     constexpr bool FWD = MODE == kFwd || RHO;
     __shared__ double mred[MOM ? 4 * (kBlock / 64) : 1];
     double s_m = 0.0, s_a = 0.0, s_q = 0.0;   // W2 f, W2 |f|, W2 f^2 of this line
+    // FP64 64-line tiles with the density: each line's weights, shift,
+    // density weight and |v|^2, for the evaluation by line groups
+    constexpr bool LG = RHO && sizeof(T) == 8;
+    __shared__ T pw[LG ? 4 * 64 : 1];
+    __shared__ int ps[LG ? 64 : 1];
+    __shared__ double pwk[LG ? 64 : 1], pvv[LG ? 64 : 1];
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[MODE == kDshift ? kBlock : 1];
     const int n = sp.n;
@@ -367,6 +373,20 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         w2 = wq[2];
         w3 = wq[3];
     }
+    if (LG && L == 64 && threadIdx.x < 64) {
+        // (the first segment's thread of every line; all 64 lines are whole)
+        pw[4 * l] = w0;
+        pw[4 * l + 1] = w1;
+        pw[4 * l + 2] = w2;
+        pw[4 * l + 3] = w3;
+        ps[l] = s;
+        const int v1 = static_cast<int>(kl / rf.n4);
+        const int v2 = static_cast<int>(kl - static_cast<int64_t>(v1) * rf.n4);
+        pwk[l] = rf.g3.w[v1 % rf.g3.m] * rf.g3.h * (rf.g4.w[v2 % rf.g4.m] * rf.g4.h);
+        const double a1 = rf.g3.lo + (static_cast<double>(v1) + rf.g3.xi[0]) * rf.g3.h;
+        const double a2 = rf.g4.lo + (static_cast<double>(v2) + rf.g4.xi[0]) * rf.g4.h;
+        pvv[l] = a1 * a1 + a2 * a2;
+    }
     __syncthreads();
     if (MODE == kAdj) transposed_taps<T>(buf + l, L, b, e, s, n, w0, w1, w2, w3, active);
     spline_solve_segment<T>(buf + l, L, b, e, active, sp);
@@ -376,6 +396,88 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
             for (int i = b; i < e; ++i) dst[static_cast<int64_t>(i) * inner] = buf[i * L + l];
         }
         return;
+    }
+    if constexpr (LG) {
+        if (L == 64) {
+            // FP64 evaluation by (line group, row segment): a group of 16
+            // lanes (128 contiguous bytes of a row) makes the outputs of lines
+            // gi, gi+16, gi+32, gi+48 at the R = n/16 rows of one segment
+            // (R <= 6: a 64-line FP64 tile holds at most 96 points a line).
+            // Each thread adds its lines' weighted values per row in
+            // registers; only the 16 lanes of a group are reduced across.
+            // (In FP32 the per-line evaluation below is faster: it needs
+            // fewer registers at the higher occupancy of FP32 tiles.)
+            constexpr int kR = 6;
+            const int lane = threadIdx.x & 63;
+            const int gi = threadIdx.x & 15;
+            const int R = n / 16;
+            const int r0 = (static_cast<int>(threadIdx.x) >> 4) * R;
+            const double w2x = rf.g2.h;
+            T* __restrict__ tile = fout + o * n * inner + (kl - l);
+            double qm[4] = {0.0, 0.0, 0.0, 0.0};
+            double rs[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) rs[t] = 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int ln = gi + 16 * c;
+                const T a0 = pw[4 * ln], a1 = pw[4 * ln + 1];
+                const T a2 = pw[4 * ln + 2], a3 = pw[4 * ln + 3];
+                const double wkl = pwk[ln];
+                const double wm = wkl * w2x;
+                const double vv = MOM ? pvv[ln] : 0.0;
+                T* __restrict__ dl = tile + ln;
+                int j = first_tap(r0, ps[ln], n);
+                T c0 = buf[j * 64 + ln];
+                j = next_idx(j, n);
+                T c1 = buf[j * 64 + ln];
+                j = next_idx(j, n);
+                T c2 = buf[j * 64 + ln];
+                j = next_idx(j, n);
+                T c3 = buf[j * 64 + ln];
+#pragma unroll
+                for (int r = 0; r < kR; ++r) {
+                    if (r < R) {
+                        const T ov = fma(a3, c3, fma(a2, c2, fma(a1, c1, a0 * c0)));
+                        dl[static_cast<int64_t>(r0 + r) * inner] = ov;
+                        const double od = static_cast<double>(ov);
+                        rs[r] = fma(wkl, od, rs[r]);
+                        if (MOM) {
+                            qm[0] = fma(wm, od, qm[0]);
+                            qm[1] = fma(wm, fabs(od), qm[1]);
+                            qm[2] = fma(wm * od, od, qm[2]);
+                            qm[3] = fma(wm * vv, od, qm[3]);
+                        }
+                        c0 = c1;
+                        c1 = c2;
+                        c2 = c3;
+                        j = next_idx(j, n);
+                        c3 = buf[j * 64 + ln];
+                    }
+                }
+            }
+            const double rr = group_reduce_scatter<8, 16>(rs, lane);
+            if (gi < R) rf.part[static_cast<int64_t>(blockIdx.x) * n + r0 + gi] = rr;
+            if (MOM) {
+                const double w1x = rf.g1.h;
+                const int wave = threadIdx.x >> 6;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    double v = w1x * qm[t];
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                    if (lane == 0) mred[t * (kBlock / 64) + wave] = v;
+                }
+                __syncthreads();
+                if (threadIdx.x < 4) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int w = 0; w < kBlock / 64; ++w) t += mred[threadIdx.x * (kBlock / 64) + w];
+                    rf.mom_part[static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x] = t;
+                }
+            }
+            return;
+        }
     }
     double acc = 0.0;
     if (active) {
@@ -722,7 +824,8 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
         const int L = tile_lines(n, sizeof(T));
         const size_t lds = static_cast<size_t>(n) * L * sizeof(T);
         if ((MODE == kFwdRho || MODE == kFwdRhoMom) &&
-            (axis != 1 || (L != 64 && L != 32) || inner % L || n % (kBlock / L)))
+            (axis != 1 || (L != 64 && L != 32) || inner % L || n % (kBlock / L) ||
+             (L == 64 && sizeof(T) == 8 && (n % 16 || n > 96))))
             return set_error(VP_ERR_UNSUPPORTED,
                              "fused x2 sweep needs 32- or 64-line tiles of equal segments");
         if (lds > kTileBytes)
@@ -808,6 +911,8 @@ int spline_rho_group(vp_dtype dt, const int64_t dims[4]) {
     const int L = tile_lines(static_cast<int>(dims[1]), dtype_size(dt));
     if (L != 64 && L != 32) return 0;
     if ((dims[2] * dims[3]) % L || dims[1] % (kBlock / L)) return 0;
+    // 16 row segments of the FP64 evaluation by line groups
+    if (L == 64 && dt == VP_F64 && dims[1] % 16) return 0;
     return L;
 }
 
