@@ -29,7 +29,7 @@ namespace vp {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kU = 8;  // loads issued back to back per thread
+constexpr int kU = 4;  // rows per wavefront pass of the row shift derivative
 
 template <typename T>
 struct SplineParams {
@@ -743,45 +743,49 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         }
         return;
     }
-    // shift derivative: kU rows per wavefront at a time, their lam loads
-    // issued back to back (clamped indices), one FP64 sum per row
+    // shift derivative: kU rows per wavefront at a time (rows r0 + u kWaves),
+    // each row's weights and shift in registers, lanes over the columns; the
+    // kU row sums of the wavefront are reduced together (reduce-scatter).
+    // (Few rows per pass keep the registers, and so the occupancy that hides
+    // the lam loads, at the level of the forward sweep.)
     for (int r0 = wave; r0 < nr; r0 += kWaves * kU) {
         double acc[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) acc[u] = 0.0;
-        for (int i0 = 0; i0 < n; i0 += 64) {
-            const int i = i0 + lane;
-            const int ic = i < n ? i : n - 1;
-            T lv[kU];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int r = r0 + u * kWaves;
-                lv[u] = lam[(row0 + (r < nr ? r : nr - 1)) * n + ic];
-            }
+        for (int u = 0; u < kU; ++u) {
+            const int r = r0 + u * kWaves;
+            if (r < nr) {
+                const T* row = buf + r * ld;
+                const T* __restrict__ lrow = lam + (row0 + r) * n;
+                const T w0 = wts[4 * r + 0], w1 = wts[4 * r + 1];
+                const T w2 = wts[4 * r + 2], w3 = wts[4 * r + 3];
+                const int s = sh[r];
+                // the first two column blocks unrolled (their loads issued
+                // together across the kU rows), the rest of a long row after
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int r = r0 + u * kWaves;
-                if (r < nr && i < n) {
-                    const T* row = buf + r * ld;
-                    const int s = sh[r];
+                for (int c = 0; c < 2; ++c) {
+                    const int i = c * 64 + lane;
+                    if (i < n) {
+                        const int j0 = first_tap(i, s, n);
+                        const int j1 = next_idx(j0, n), j2 = next_idx(j1, n);
+                        const int j3 = next_idx(j2, n);
+                        const T v = fma(w3, row[j3], fma(w2, row[j2], fma(w1, row[j1], w0 * row[j0])));
+                        acc[u] = fma(static_cast<double>(lrow[i]), static_cast<double>(v), acc[u]);
+                    }
+                }
+                for (int i = 128 + lane; i < n; i += 64) {
                     const int j0 = first_tap(i, s, n);
                     const int j1 = next_idx(j0, n), j2 = next_idx(j1, n);
                     const int j3 = next_idx(j2, n);
-                    const T v = fma(wts[4 * r + 3], row[j3],
-                                    fma(wts[4 * r + 2], row[j2],
-                                        fma(wts[4 * r + 1], row[j1], wts[4 * r] * row[j0])));
-                    acc[u] = fma(static_cast<double>(lv[u]), static_cast<double>(v), acc[u]);
+                    const T v = fma(w3, row[j3], fma(w2, row[j2], fma(w1, row[j1], w0 * row[j0])));
+                    acc[u] = fma(static_cast<double>(lrow[i]), static_cast<double>(v), acc[u]);
                 }
             }
         }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            double a = acc[u];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
-            const int r = r0 + u * kWaves;
-            if (lane == 0 && r < nr) g[row0 + r] = a;
-        }
+        // lane u (< kU) receives the sum of row r0 + u kWaves
+        const double a = group_reduce_scatter<kU, 64>(acc, lane);
+        if (lane < kU && r0 + lane * kWaves < nr) g[row0 + r0 + lane * kWaves] = a;
     }
 }
 

@@ -50,6 +50,24 @@ def test_adjoint_sweeps_and_shift_derivatives(method, dt):
         assert_close(to_host(g), gref.reshape(-1), dt, f"dshift axis {axis}")
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("n", [100, 150, 257])
+def test_spline_shift_derivative_long_contiguous_rows(dt, n):
+    # rows of the contiguous axis longer than one and two wavefronts (the
+    # unrolled column blocks and the loop after them), a ragged last tile
+    vp = require_gpu()
+    dims = (3, 4, 5, n)
+    u = random_field(dims, seed=11)
+    lam = random_field(dims, seed=12)
+    ud, ld = to_dev(u, dt), to_dev(lam, dt)
+    sig = _line_shifts(dims, 3, seed=13, n_cells=n, scale=4.0)
+    g = torch.empty(int(np.prod(dims[:3])), dtype=torch.float64, device="cuda")
+    announce(f"spline dshift {dt} n={n}")
+    vp.spline_advect_dshift(3, ud, ld, to_dev(sig), g)
+    gref = adjoint.spline_sweep_dshift(to_host(ud), to_host(ld), 3, sig)
+    assert_close(to_host(g), gref.reshape(-1), dt, "dshift along the contiguous axis")
+
+
 @pytest.mark.parametrize("degree", [2, -1])
 def test_density_and_poisson_adjoint(degree):
     vp = require_gpu()
