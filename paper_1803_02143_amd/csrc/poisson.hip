@@ -17,9 +17,11 @@
 // Three kernels (plus a one-block sum when W is asked for):
 //   rows_fwd  one workgroup per x1 row: Q map along both axes, DFT along x2
 //   cols      one workgroup per x2 mode: DFT along x1, spectral solve,
-//             inverse DFT along x1 of both field components
-//   rows_inv  one workgroup per cell row (m rows): inverse DFT along x2,
-//             Q^{-1} map, E (and optionally the v-sweep shifts tau E/h_v),
+//             inverse DFT along x1 of both field components, Q^{-1} map
+//             along x1 (real coefficients: it commutes with the transform
+//             along x2 and the real part taken after it)
+//   rows_inv  one workgroup per x1 row: inverse DFT along x2, Q^{-1} map
+//             along x2, E (and optionally the v-sweep shifts tau E/h_v),
 //             per-workgroup energy partial sums
 #include <cmath>
 
@@ -100,12 +102,12 @@ rows_fwd(const double* __restrict__ rho, Cplx* __restrict__ c1, int n1, int n2,
 
 __global__ void __launch_bounds__(kPB)
 cols(const Cplx* __restrict__ c1, Cplx* __restrict__ g1, Cplx* __restrict__ g2,
-     int n1, int n2, double L1, double L2) {
+     int n1, int n2, double L1, double L2, Transfer tinv, int use_q) {
     extern __shared__ __align__(16) unsigned char smem[];
     Cplx* tw = reinterpret_cast<Cplx*>(smem);  // n1
     Cplx* col = tw + n1;                       // n1
-    Cplx* e1h = col + n1;                      // n1
-    Cplx* e2h = e1h + n1;                      // n1
+    Cplx* eh = col + n1;                       // 2 n1: E1 hat, E2 hat
+    Cplx* ex = eh + 2 * n1;                    // 2 n1: their inverse transforms
     const int k2 = blockIdx.x;
     twiddles(tw, n1);
     for (int a = threadIdx.x; a < n1; a += kPB) col[a] = c1[static_cast<int64_t>(a) * n2 + k2];
@@ -129,57 +131,52 @@ cols(const Cplx* __restrict__ c1, Cplx* __restrict__ g1, Cplx* __restrict__ g2,
         const double kx = 2.0 * M_PI * m1 / L1;
         const double kk = kx * kx + ky * ky;
         if (nyq || kk == 0.0) {
-            e1h[k1] = Cplx{0.0, 0.0};
-            e2h[k1] = Cplx{0.0, 0.0};
+            eh[k1] = Cplx{0.0, 0.0};
+            eh[n1 + k1] = Cplx{0.0, 0.0};
         } else {
             // -i k (re + i im) / |k|^2 = k (im - i re) / |k|^2
             const double s1 = kx / kk, s2 = ky / kk;
-            e1h[k1] = Cplx{s1 * im, -s1 * re};
-            e2h[k1] = Cplx{s2 * im, -s2 * re};
+            eh[k1] = Cplx{s1 * im, -s1 * re};
+            eh[n1 + k1] = Cplx{s2 * im, -s2 * re};
         }
     }
     __syncthreads();
-    for (int a = threadIdx.x; a < n1; a += kPB) {
-        double r1 = 0.0, i1 = 0.0, r2 = 0.0, i2 = 0.0;
+    // inverse transforms: one thread per (component, x1 point)
+    for (int e = threadIdx.x; e < 2 * n1; e += kPB) {
+        const int d = e >= n1 ? 1 : 0;
+        const int a = e - d * n1;
+        const Cplx* x = eh + d * n1;
+        double re = 0.0, im = 0.0;
         int idx = 0;
         for (int k1 = 0; k1 < n1; ++k1) {
             const Cplx w = tw[idx];       // conj(w) for the inverse transform
-            const Cplx x = e1h[k1], y = e2h[k1];
-            r1 = fma(x.re, w.re, fma(x.im, w.im, r1));
-            i1 = fma(x.im, w.re, fma(-x.re, w.im, i1));
-            r2 = fma(y.re, w.re, fma(y.im, w.im, r2));
-            i2 = fma(y.im, w.re, fma(-y.re, w.im, i2));
+            re = fma(x[k1].re, w.re, fma(x[k1].im, w.im, re));
+            im = fma(x[k1].im, w.re, fma(-x[k1].re, w.im, im));
             idx += a;
             if (idx >= n1) idx -= n1;
         }
-        g1[static_cast<int64_t>(a) * n2 + k2] = Cplx{r1, i1};
-        g2[static_cast<int64_t>(a) * n2 + k2] = Cplx{r2, i2};
+        ex[e] = Cplx{re, im};
     }
-}
-
-// Inverse DFT along x2 of m rows of g into eq[m][n2] (real part, scaled).
-__device__ __forceinline__ void inverse_rows(const Cplx* __restrict__ g, int a0,
-                                             int m, int n1, int n2, const Cplx* tw,
-                                             Cplx* gl, double* eq) {
-    for (int e = threadIdx.x; e < m * n2; e += kPB)
-        gl[e] = g[static_cast<int64_t>(a0) * n2 + e];
     __syncthreads();
-    const double scale = 1.0 / (static_cast<double>(n1) * n2);
-    for (int e = threadIdx.x; e < m * n2; e += kPB) {
-        const int p = e / n2;
-        const int b = e - p * n2;
-        const Cplx* row = gl + p * n2;
-        double s = 0.0;
-        int idx = 0;
-        for (int k = 0; k < n2; ++k) {
-            // Re[(x.re + i x.im)(w.re - i w.im)] = x.re w.re + x.im w.im
-            s = fma(row[k].re, tw[idx].re, fma(row[k].im, tw[idx].im, s));
-            idx += b;
-            if (idx >= n2) idx -= n2;
+    for (int e = threadIdx.x; e < 2 * n1; e += kPB) {
+        const int d = e >= n1 ? 1 : 0;
+        const int a = e - d * n1;
+        Cplx v;
+        if (use_q) {
+            // Q^{-1} along x1 within the cell of a
+            const int m = tinv.m;
+            const int pa = a % m, a0 = a - pa;
+            v = Cplx{0.0, 0.0};
+            for (int p = 0; p < m; ++p) {
+                const Cplx y = ex[d * n1 + a0 + p];
+                v.re = fma(tinv.q[pa][p], y.re, v.re);
+                v.im = fma(tinv.q[pa][p], y.im, v.im);
+            }
+        } else {
+            v = ex[e];
         }
-        eq[e] = s * scale;
+        (d ? g2 : g1)[static_cast<int64_t>(a) * n2 + k2] = v;
     }
-    __syncthreads();
 }
 
 __global__ void __launch_bounds__(kPB)
@@ -190,49 +187,63 @@ rows_inv(const Cplx* __restrict__ g1, const Cplx* __restrict__ g2,
          double* __restrict__ sig2, double s1, double s2) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[kPB / 64];
-    const int m = use_q ? t.m : 1;
-    Cplx* tw = reinterpret_cast<Cplx*>(smem);   // n2
-    Cplx* gl = tw + n2;                         // m * n2
-    double* eq1 = reinterpret_cast<double*>(gl + m * n2);  // m * n2
-    double* eq2 = eq1 + m * n2;                             // m * n2
-    const int a0 = blockIdx.x * m;
+    Cplx* tw = reinterpret_cast<Cplx*>(smem);            // n2
+    Cplx* gl = tw + n2;                                  // 2 n2: the row of g1, g2
+    double* eq = reinterpret_cast<double*>(gl + 2 * n2);  // 2 n2
+    const int a = blockIdx.x;
     twiddles(tw, n2);
-    inverse_rows(g1, a0, m, n1, n2, tw, gl, eq1);
-    inverse_rows(g2, a0, m, n1, n2, tw, gl, eq2);
+    for (int b = threadIdx.x; b < n2; b += kPB) {
+        gl[b] = g1[static_cast<int64_t>(a) * n2 + b];
+        gl[n2 + b] = g2[static_cast<int64_t>(a) * n2 + b];
+    }
+    __syncthreads();
+    // inverse DFT along x2, real part, one thread per (component, x2 point)
+    const double scale = 1.0 / (static_cast<double>(n1) * n2);
+    for (int e = threadIdx.x; e < 2 * n2; e += kPB) {
+        const int d = e >= n2 ? 1 : 0;
+        const int b = e - d * n2;
+        const Cplx* row = gl + d * n2;
+        double sum = 0.0;
+        int idx = 0;
+        for (int k = 0; k < n2; ++k) {
+            // Re[(x.re + i x.im)(w.re - i w.im)] = x.re w.re + x.im w.im
+            sum = fma(row[k].re, tw[idx].re, fma(row[k].im, tw[idx].im, sum));
+            idx += b;
+            if (idx >= n2) idx -= n2;
+        }
+        eq[e] = sum * scale;
+    }
+    __syncthreads();
     double wsum = 0.0;
-    for (int e = threadIdx.x; e < m * n2; e += kPB) {
-        const int p = e / n2;
-        const int b = e - p * n2;
+    const double wa = gx1.w[a % gx1.m] * gx1.h;
+    for (int b = threadIdx.x; b < n2; b += kPB) {
         double v1, v2;
         if (use_q) {
+            // Q^{-1} along x2 within the cell of b
+            const int m = t.m;
             const int pb = b % m, b0 = b - pb;
             v1 = 0.0;
             v2 = 0.0;
-            for (int pp = 0; pp < m; ++pp) {
-                double r1 = 0.0, r2 = 0.0;
-                for (int q = 0; q < m; ++q) {
-                    r1 = fma(t.q[pb][q], eq1[pp * n2 + b0 + q], r1);
-                    r2 = fma(t.q[pb][q], eq2[pp * n2 + b0 + q], r2);
-                }
-                v1 = fma(t.q[p][pp], r1, v1);
-                v2 = fma(t.q[p][pp], r2, v2);
+            for (int q = 0; q < m; ++q) {
+                v1 = fma(t.q[pb][q], eq[b0 + q], v1);
+                v2 = fma(t.q[pb][q], eq[n2 + b0 + q], v2);
             }
         } else {
-            v1 = eq1[e];
-            v2 = eq2[e];
+            v1 = eq[b];
+            v2 = eq[n2 + b];
         }
-        const int64_t gi = static_cast<int64_t>(a0 + p) * n2 + b;
+        const int64_t gi = static_cast<int64_t>(a) * n2 + b;
         E1[gi] = v1;
         E2[gi] = v2;
         if (sig1) {
             sig1[gi] = s1 * v1;
             sig2[gi] = s2 * v2;
         }
-        const double w = gx1.w[(a0 + p) % gx1.m] * gx1.h * gx2.w[b % gx2.m] * gx2.h;
+        const double w = wa * (gx2.w[b % gx2.m] * gx2.h);
         wsum = fma(w, v1 * v1 + v2 * v2, wsum);
     }
     const double tot = block_sum(wsum, red);
-    if (threadIdx.x == 0) wpart[blockIdx.x] = tot;
+    if (threadIdx.x == 0) wpart[a] = tot;
 }
 
 __global__ void __launch_bounds__(kPB)
@@ -364,6 +375,31 @@ adj_cols(const Cplx* __restrict__ c1, const Cplx* __restrict__ c2, Cplx* __restr
     }
 }
 
+// Inverse DFT along x2 of m rows of g into eq[m][n2] (real part, scaled).
+__device__ __forceinline__ void inverse_rows(const Cplx* __restrict__ g, int a0,
+                                             int m, int n1, int n2, const Cplx* tw,
+                                             Cplx* gl, double* eq) {
+    for (int e = threadIdx.x; e < m * n2; e += kPB)
+        gl[e] = g[static_cast<int64_t>(a0) * n2 + e];
+    __syncthreads();
+    const double scale = 1.0 / (static_cast<double>(n1) * n2);
+    for (int e = threadIdx.x; e < m * n2; e += kPB) {
+        const int p = e / n2;
+        const int b = e - p * n2;
+        const Cplx* row = gl + p * n2;
+        double s = 0.0;
+        int idx = 0;
+        for (int k = 0; k < n2; ++k) {
+            // Re[(x.re + i x.im)(w.re - i w.im)] = x.re w.re + x.im w.im
+            s = fma(row[k].re, tw[idx].re, fma(row[k].im, tw[idx].im, s));
+            idx += b;
+            if (idx >= n2) idx -= n2;
+        }
+        eq[e] = s * scale;
+    }
+    __syncthreads();
+}
+
 __global__ void __launch_bounds__(kPB)
 adj_rows_inv(const Cplx* __restrict__ h, double* __restrict__ rho_bar, int n1, int n2,
              Transfer t, int use_q) {
@@ -401,9 +437,15 @@ static size_t poisson_ws_bytes(int64_t n1, int64_t n2) {
            sizeof(double) * static_cast<size_t>(n1) + 256;
 }
 
-static size_t rows_inv_lds(int m, int n2) {
+static size_t rows_inv_lds(int n2) {
+    return sizeof(Cplx) * 3 * static_cast<size_t>(n2) + 2 * sizeof(double) * static_cast<size_t>(n2);
+}
+
+static size_t cols_lds(int n1) { return sizeof(Cplx) * 6 * static_cast<size_t>(n1); }
+
+static size_t adj_rows_inv_lds(int m, int n2) {
     return sizeof(Cplx) * (static_cast<size_t>(n2) + static_cast<size_t>(m) * n2) +
-           2 * sizeof(double) * static_cast<size_t>(m) * n2;
+           sizeof(double) * static_cast<size_t>(m) * n2;
 }
 
 vp_status poisson_impl_shift(int degree, int64_t n1_, int64_t n2_, double L1, double L2,
@@ -418,11 +460,9 @@ vp_status poisson_impl_shift(int degree, int64_t n1_, int64_t n2_, double L1, do
     double* wpart = reinterpret_cast<double*>(g2 + n);
     Transfer t{};
     const bool sldg = degree >= 0;
-    int m = 1;
     Transfer tinv{};
     if (sldg) {
         const TransferPair& tp = transfer_pair(degree);
-        m = tp.m;
         t.m = tinv.m = tp.m;
         for (int i = 0; i < tp.m; ++i)
             for (int j = 0; j < tp.m; ++j) {
@@ -430,8 +470,8 @@ vp_status poisson_impl_shift(int degree, int64_t n1_, int64_t n2_, double L1, do
                 tinv.q[i][j] = tp.qinv[i][j];
             }
     }
-    const size_t lds_inv = rows_inv_lds(m, n2);
-    if (lds_inv > 64 * 1024 || static_cast<size_t>(4 * n1) * sizeof(Cplx) > 64 * 1024)
+    const size_t lds_inv = rows_inv_lds(n2);
+    if (lds_inv > 64 * 1024 || cols_lds(n1) > 64 * 1024)
         return set_error(VP_ERR_UNSUPPORTED, "x grid %d x %d too large for the Poisson kernels",
                          n1, n2);
     const AxisGrid gx1 = axis_grid(degree, n1_, 0.0, L1);
@@ -440,9 +480,9 @@ vp_status poisson_impl_shift(int degree, int64_t n1_, int64_t n2_, double L1, do
                                                                      sldg ? 1 : 0);
     vp_status rc = check_launch("rows_fwd");
     if (rc != VP_OK) return rc;
-    cols<<<n2, kPB, 4 * n1 * sizeof(Cplx), st>>>(c1, g1, g2, n1, n2, L1, L2);
+    cols<<<n2, kPB, cols_lds(n1), st>>>(c1, g1, g2, n1, n2, L1, L2, tinv, sldg ? 1 : 0);
     if ((rc = check_launch("cols")) != VP_OK) return rc;
-    const int nb = n1 / m;
+    const int nb = n1;
     rows_inv<<<nb, kPB, lds_inv, st>>>(g1, g2, E1, E2, n1, n2, tinv, sldg ? 1 : 0, gx1,
                                        gx2, wpart, sig1, sig2, s1, s2);
     if ((rc = check_launch("rows_inv")) != VP_OK) return rc;
@@ -481,7 +521,7 @@ vp_status poisson_adjoint_impl(int degree, int64_t n1_, int64_t n2_, double L1, 
                 tinv.q[i][j] = tp.qinv[i][j];
             }
     }
-    if (rows_inv_lds(m, n2) > 64 * 1024 || static_cast<size_t>(4 * n1) * sizeof(Cplx) > 64 * 1024)
+    if (adj_rows_inv_lds(m, n2) > 64 * 1024 || static_cast<size_t>(4 * n1) * sizeof(Cplx) > 64 * 1024)
         return set_error(VP_ERR_UNSUPPORTED, "x grid %d x %d too large for the Poisson kernels",
                          n1, n2);
     const AxisGrid gx1 = axis_grid(degree, n1_, 0.0, L1);
@@ -492,8 +532,7 @@ vp_status poisson_adjoint_impl(int degree, int64_t n1_, int64_t n2_, double L1, 
     if (rc != VP_OK) return rc;
     adj_cols<<<n2, kPB, 4 * n1 * sizeof(Cplx), st>>>(c1, c2, h, n1, n2, L1, L2);
     if ((rc = check_launch("adj_cols")) != VP_OK) return rc;
-    adj_rows_inv<<<n1 / m, kPB, sizeof(Cplx) * (n2 + static_cast<size_t>(m) * n2) +
-                                     sizeof(double) * static_cast<size_t>(m) * n2, st>>>(
+    adj_rows_inv<<<n1 / m, kPB, adj_rows_inv_lds(m, n2), st>>>(
         h, rho_bar, n1, n2, t, sldg ? 1 : 0);
     return check_launch("adj_rows_inv");
 }
