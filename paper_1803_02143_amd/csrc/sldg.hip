@@ -203,7 +203,7 @@ __device__ __forceinline__ void sldg_cell(const T A[M][M], const T B[M][M],
         for (int l = 0; l < M; ++l) acc = fma(A[j][l], left[l], acc);
 #pragma unroll
         for (int l = 0; l < M; ++l) acc = fma(B[j][l], right[l], acc);
-        out[j * stride] = acc;
+        put_out(&out[j * stride], acc);
     }
 }
 
@@ -338,7 +338,7 @@ sldg_col_rho(const T* __restrict__ fin, T* __restrict__ fout,
                     for (int l = 0; l < M; ++l) acc = fma(A[j][l], prev[l], acc);
 #pragma unroll
                     for (int l = 0; l < M; ++l) acc = fma(B[j][l], cur[u][l], acc);
-                    dst[(i + u) * cs + j * inner] = acc;
+                    put_out(&dst[(i + u) * cs + j * inner], acc);
                     const double ov = static_cast<double>(acc);
                     vals[(u - h) * M + j] = wk * ov;
                     if (MOM) {
@@ -376,7 +376,7 @@ sldg_col_rho(const T* __restrict__ fin, T* __restrict__ fout,
             for (int l = 0; l < M; ++l) acc = fma(A[j][l], prev[l], acc);
 #pragma unroll
             for (int l = 0; l < M; ++l) acc = fma(B[j][l], cur[l], acc);
-            dst[i * cs + j * inner] = acc;
+            put_out(&dst[i * cs + j * inner], acc);
             const double ov = static_cast<double>(acc);
             vals[j] = wk * ov;
             if (MOM) {
@@ -498,7 +498,7 @@ sldg_row(const T* __restrict__ fin, T* __restrict__ fout,
             }
             if (q0 + b * kBlock < ncell) {
 #pragma unroll
-                for (int j = 0; j < M; ++j) o0[q * M + j] = out[j];
+                for (int j = 0; j < M; ++j) put_out(&o0[q * M + j], out[j]);
             }
         }
     }

@@ -393,7 +393,7 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     if (MODE == kAdj) {
         if (active) {
             T* __restrict__ dst = fout + lbase;
-            for (int i = b; i < e; ++i) dst[static_cast<int64_t>(i) * inner] = buf[i * L + l];
+            for (int i = b; i < e; ++i) put_out(&dst[static_cast<int64_t>(i) * inner], buf[i * L + l]);
         }
         return;
     }
@@ -439,7 +439,7 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                 for (int r = 0; r < kR; ++r) {
                     if (r < R) {
                         const T ov = fma(a3, c3, fma(a2, c2, fma(a1, c1, a0 * c0)));
-                        dl[static_cast<int64_t>(r0 + r) * inner] = ov;
+                        put_out(&dl[static_cast<int64_t>(r0 + r) * inner], ov);
                         const double od = static_cast<double>(ov);
                         rs[r] = fma(wkl, od, rs[r]);
                         if (MOM) {
@@ -509,10 +509,10 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                 const T o1 = fma(w3, c4, fma(w2, c3, fma(w1, c2, w0 * c1)));
                 const T o2 = fma(w3, c5, fma(w2, c4, fma(w1, c3, w0 * c2)));
                 const T o3 = fma(w3, c6, fma(w2, c5, fma(w1, c4, w0 * c3)));
-                dst[static_cast<int64_t>(i) * inner] = o0;
-                dst[static_cast<int64_t>(i + 1) * inner] = o1;
-                dst[static_cast<int64_t>(i + 2) * inner] = o2;
-                dst[static_cast<int64_t>(i + 3) * inner] = o3;
+                put_out(&dst[static_cast<int64_t>(i) * inner], o0);
+                put_out(&dst[static_cast<int64_t>(i + 1) * inner], o1);
+                put_out(&dst[static_cast<int64_t>(i + 2) * inner], o2);
+                put_out(&dst[static_cast<int64_t>(i + 3) * inner], o3);
                 if (RHO) {
                     // the wavefront's 64 lines share i: sums over them
                     double vals[4] = {wk * static_cast<double>(o0), wk * static_cast<double>(o1),
@@ -545,7 +545,7 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         if (FWD) {
             for (; i < e; ++i) {
                 const T o = fma(w3, c3, fma(w2, c2, fma(w1, c1, w0 * c0)));
-                dst[static_cast<int64_t>(i) * inner] = o;
+                put_out(&dst[static_cast<int64_t>(i) * inner], o);
                 if (RHO) {
                     double vals[1] = {wk * static_cast<double>(o)};
                     if (MOM) {
@@ -705,7 +705,7 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
             const T* row = buf + r * ld;
             T* __restrict__ dst = fout + (row0 + r) * n;
             if (MODE == kAdj) {
-                for (int i = lane; i < n; i += 64) dst[i] = row[i];
+                for (int i = lane; i < n; i += 64) put_out(&dst[i], row[i]);
                 continue;
             }
             const T w0 = wts[4 * r + 0], w1 = wts[4 * r + 1];
@@ -714,7 +714,7 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
             for (int i = lane; i < n; i += 64) {
                 const int j0 = first_tap(i, s, n);
                 const int j1 = next_idx(j0, n), j2 = next_idx(j1, n), j3 = next_idx(j2, n);
-                dst[i] = fma(w3, row[j3], fma(w2, row[j2], fma(w1, row[j1], w0 * row[j0])));
+                put_out(&dst[i], fma(w3, row[j3], fma(w2, row[j2], fma(w1, row[j1], w0 * row[j0]))));
             }
         }
         return;
@@ -727,12 +727,12 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         for (int e = threadIdx.x; e < cnt; e += kBlock) {
             const T* row = buf + r * ld;
             if (MODE == kAdj) {
-                dst[e] = row[i];
+                put_out(&dst[e], row[i]);
             } else {
                 const int j0 = first_tap(i, sh[r], n);
                 const int j1 = next_idx(j0, n), j2 = next_idx(j1, n), j3 = next_idx(j2, n);
                 const T* w = wts + 4 * r;
-                dst[e] = fma(w[3], row[j3], fma(w[2], row[j2], fma(w[1], row[j1], w[0] * row[j0])));
+                put_out(&dst[e], fma(w[3], row[j3], fma(w[2], row[j2], fma(w[1], row[j1], w[0] * row[j0]))));
             }
             r += dr;
             i += di;

@@ -171,6 +171,15 @@ __device__ __forceinline__ double group_reduce_scatter(double* v, int lane) {
     return r;
 }
 
+// Store of a sweep output.  Every output element is written once and read
+// only by a later kernel, so the store is non-temporal: the line streams out
+// to memory during this kernel instead of waiting dirty in the caches, where
+// its write-back would fall into the next sweep.
+template <typename T>
+__device__ __forceinline__ void put_out(T* p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
+
 // Launch geometry helpers.
 inline unsigned blocks_for(int64_t work, int per_block) {
     return static_cast<unsigned>((work + per_block - 1) / per_block);
