@@ -497,8 +497,16 @@ sldg_row(const T* __restrict__ fin, T* __restrict__ fout,
                 out[j] = acc;
             }
             if (q0 + b * kBlock < ncell) {
+                // (FP64: a lane's M-element run leaves every line partly
+                // written per store instruction; streamed, those partial
+                // lines cost extra write traffic, so FP64 rows stay cached)
 #pragma unroll
-                for (int j = 0; j < M; ++j) put_out(&o0[q * M + j], out[j]);
+                for (int j = 0; j < M; ++j) {
+                    if constexpr (sizeof(T) == 4)
+                        put_out(&o0[q * M + j], out[j]);
+                    else
+                        o0[q * M + j] = out[j];
+                }
             }
         }
     }
