@@ -21,6 +21,7 @@
 // contiguous axis as [R][n+1] (padded against LDS bank conflicts).  One
 // thread per line runs the two recursions; all threads load, evaluate and
 // store element-parallel with contiguous global accesses.
+#include <algorithm>
 #include <cmath>
 
 #include "field.hpp"
@@ -380,8 +381,9 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         pw[4 * l + 2] = w2;
         pw[4 * l + 3] = w3;
         ps[l] = s;
-        const int v1 = static_cast<int>(kl / rf.n4);
-        const int v2 = static_cast<int>(kl - static_cast<int64_t>(v1) * rf.n4);
+        const int k32 = static_cast<int>(kl);   // velocity index (< 2^31 here)
+        const int v1 = k32 / rf.n4;
+        const int v2 = k32 - v1 * rf.n4;
         pwk[l] = rf.g3.w[v1 % rf.g3.m] * rf.g3.h * (rf.g4.w[v2 % rf.g4.m] * rf.g4.h);
         const double a1 = rf.g3.lo + (static_cast<double>(v1) + rf.g3.xi[0]) * rf.g3.h;
         const double a2 = rf.g4.lo + (static_cast<double>(v2) + rf.g4.xi[0]) * rf.g4.h;
@@ -456,23 +458,48 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                     }
                 }
             }
-            const double rr = group_reduce_scatter<8, 16>(rs, lane);
-            if (gi < R) rf.part[static_cast<int64_t>(blockIdx.x) * n + r0 + gi] = rr;
+            // Sums through the (now free) tile, no cross-lane exchanges:
+            // thread (gi, p) puts its R row partials at
+            // red_rows[(p R + r) 17 + gi] (rows padded to 17 against bank
+            // conflicts) and, with the moments, its four moment partials at
+            // red_mom[q 256 + t].  After a barrier thread i < n adds the 16
+            // line groups of row i in order; the last wavefront (idle there,
+            // n <= 96) adds the moment partials in 64 strided chunks of 16,
+            // and after another barrier four threads add the chunks.
+            __syncthreads();
+            double* red_rows = reinterpret_cast<double*>(smem);
+            double* red_mom = red_rows + n * 17;      // [4][256]
+            double* red_chunk = red_mom + 4 * kBlock;  // [4][16]
+#pragma unroll
+            for (int r = 0; r < kR; ++r)
+                if (r < R) red_rows[(r0 + r) * 17 + gi] = rs[r];
             if (MOM) {
                 const double w1x = rf.g1.h;
-                const int wave = threadIdx.x >> 6;
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    double v = w1x * qm[t];
+                for (int q = 0; q < 4; ++q) red_mom[q * kBlock + threadIdx.x] = w1x * qm[q];
+            }
+            __syncthreads();
+            if (static_cast<int>(threadIdx.x) < n) {
+                const double* q = red_rows + threadIdx.x * 17;
+                double t = 0.0;
 #pragma unroll
-                    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-                    if (lane == 0) mred[t * (kBlock / 64) + wave] = v;
+                for (int g = 0; g < 16; ++g) t += q[g];
+                rf.part[static_cast<int64_t>(blockIdx.x) * n + threadIdx.x] = t;
+            }
+            if (MOM) {
+                if (threadIdx.x >= kBlock - 64) {
+                    const int k = threadIdx.x - (kBlock - 64);
+                    const double* q = red_mom + (k >> 4) * kBlock + (k & 15);
+                    double t = 0.0;
+#pragma unroll
+                    for (int u = 0; u < kBlock / 16; ++u) t += q[16 * u];
+                    red_chunk[k] = t;
                 }
                 __syncthreads();
                 if (threadIdx.x < 4) {
                     double t = 0.0;
 #pragma unroll
-                    for (int w = 0; w < kBlock / 64; ++w) t += mred[threadIdx.x * (kBlock / 64) + w];
+                    for (int c = 0; c < 16; ++c) t += red_chunk[threadIdx.x * 16 + c];
                     rf.mom_part[static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x] = t;
                 }
             }
@@ -495,8 +522,9 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         // density weight of this line's velocity column
         double wk = 0.0;
         if (RHO) {
-            const int v1 = static_cast<int>(kl / rf.n4);
-            const int v2 = static_cast<int>(kl - static_cast<int64_t>(v1) * rf.n4);
+            const int k32 = static_cast<int>(kl);   // velocity index (< 2^31 here)
+            const int v1 = k32 / rf.n4;
+            const int v2 = k32 - v1 * rf.n4;
             wk = rf.g3.w[v1 % rf.g3.m] * rf.g3.h * (rf.g4.w[v2 % rf.g4.m] * rf.g4.h);
         }
         if (FWD) {
@@ -592,8 +620,9 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     if (MOM) {
         // workgroup sums of W f, W |f|, W f^2, W |v|^2 f (|v|^2 constant on
         // a line); every thread of the tile is active on this path
-        const int v1 = static_cast<int>(kl / rf.n4);
-        const int v2 = static_cast<int>(kl - static_cast<int64_t>(v1) * rf.n4);
+        const int k32 = static_cast<int>(kl);   // velocity index (< 2^31 here)
+        const int v1 = k32 / rf.n4;
+        const int v2 = k32 - v1 * rf.n4;
         const double a1 = rf.g3.lo + (static_cast<double>(v1) + rf.g3.xi[0]) * rf.g3.h;
         const double a2 = rf.g4.lo + (static_cast<double>(v2) + rf.g4.xi[0]) * rf.g4.h;
         const double wv = rf.g3.h * rf.g4.h;
@@ -889,9 +918,14 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
     if (axis < 3) {
         // tiles run over the flattened line index
         const int L = tile_lines(n, sizeof(T));
-        const size_t lds = static_cast<size_t>(n) * L * sizeof(T);
+        size_t lds = static_cast<size_t>(n) * L * sizeof(T);
+        // FP64 64-line tiles with the density: the tile is reused for the
+        // row sums (n rows of 17) and the moment partials (4 x 256 + 64)
+        if ((MODE == kFwdRho || MODE == kFwdRhoMom) && L == 64 && sizeof(T) == 8)
+            lds = std::max(lds, (static_cast<size_t>(n) * 17 + 4 * kBlock + 64) * sizeof(double));
         if ((MODE == kFwdRho || MODE == kFwdRhoMom) &&
             (axis != 1 || (L != 64 && L != 32) || inner % L || n % (kBlock / L) ||
+             inner >= (int64_t(1) << 31) ||
              (L == 64 && sizeof(T) == 8 && (n % 16 || n > 96))))
             return set_error(VP_ERR_UNSUPPORTED,
                              "fused x2 sweep needs 32- or 64-line tiles of equal segments");
@@ -978,6 +1012,7 @@ int spline_rho_group(vp_dtype dt, const int64_t dims[4]) {
     const int L = tile_lines(static_cast<int>(dims[1]), dtype_size(dt));
     if (L != 64 && L != 32) return 0;
     if ((dims[2] * dims[3]) % L || dims[1] % (kBlock / L)) return 0;
+    if (dims[2] * dims[3] >= (int64_t(1) << 31)) return 0;   // 32-bit velocity index
     // 16 row segments of the FP64 evaluation by line groups
     if (L == 64 && dt == VP_F64 && dims[1] % 16) return 0;
     return L;
