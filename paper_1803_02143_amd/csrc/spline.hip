@@ -293,9 +293,10 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     constexpr bool FWD = MODE == kFwd || RHO;
     __shared__ double mred[MOM ? 4 * (kBlock / 64) : 1];
     double s_m = 0.0, s_a = 0.0, s_q = 0.0;   // W2 f, W2 |f|, W2 f^2 of this line
-    // FP64 64-line tiles with the density: each line's weights, shift,
-    // density weight and |v|^2, for the evaluation by line groups
-    constexpr bool LG = RHO && sizeof(T) == 8;
+    // 64-line tiles with the density (lines of a multiple of 16 points):
+    // each line's weights, shift, density weight and |v|^2, for the
+    // evaluation by line groups
+    constexpr bool LG = RHO;
     __shared__ T pw[LG ? 4 * 64 : 1];
     __shared__ int ps[LG ? 64 : 1];
     __shared__ double pwk[LG ? 64 : 1], pvv[LG ? 64 : 1];
@@ -374,7 +375,7 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         w2 = wq[2];
         w3 = wq[3];
     }
-    if (LG && L == 64 && threadIdx.x < 64) {
+    if (LG && L == 64 && n % 16 == 0 && threadIdx.x < 64) {
         // (the first segment's thread of every line; all 64 lines are whole)
         pw[4 * l] = w0;
         pw[4 * l + 1] = w1;
@@ -400,26 +401,23 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         return;
     }
     if constexpr (LG) {
-        if (L == 64) {
-            // FP64 evaluation by (line group, row segment): a group of 16
-            // lanes (128 contiguous bytes of a row) makes the outputs of lines
-            // gi, gi+16, gi+32, gi+48 at the R = n/16 rows of one segment
-            // (R <= 6: a 64-line FP64 tile holds at most 96 points a line).
-            // Each thread adds its lines' weighted values per row in
-            // registers; only the 16 lanes of a group are reduced across.
-            // (In FP32 the per-line evaluation below is faster: it needs
-            // fewer registers at the higher occupancy of FP32 tiles.)
-            constexpr int kR = 6;
-            const int lane = threadIdx.x & 63;
+        if (L == 64 && n % 16 == 0) {
+            // Evaluation by (line group, row segment): a group of 16 lanes
+            // (one row's 16 adjacent lines) makes the outputs of lines gi,
+            // gi+16, gi+32, gi+48 at the R = n/16 rows of one segment (R <= 6
+            // in FP64, 12 in FP32: a 64-line tile holds at most 96 / 192
+            // points a line), adding their weighted values per row in
+            // registers.
+            constexpr int kR = sizeof(T) == 8 ? 6 : 12;
             const int gi = threadIdx.x & 15;
             const int R = n / 16;
             const int r0 = (static_cast<int>(threadIdx.x) >> 4) * R;
             const double w2x = rf.g2.h;
             T* __restrict__ tile = fout + o * n * inner + (kl - l);
             double qm[4] = {0.0, 0.0, 0.0, 0.0};
-            double rs[8];
+            double rs[kR];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) rs[t] = 0.0;
+            for (int t = 0; t < kR; ++t) rs[t] = 0.0;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int ln = gi + 16 * c;
@@ -441,7 +439,12 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                 for (int r = 0; r < kR; ++r) {
                     if (r < R) {
                         const T ov = fma(a3, c3, fma(a2, c2, fma(a1, c1, a0 * c0)));
-                        put_out(&dl[static_cast<int64_t>(r0 + r) * inner], ov);
+                        // (FP32: a group's 64-byte row pieces are half lines;
+                        // they stay cached to merge before write-back)
+                        if constexpr (sizeof(T) == 8)
+                            put_out(&dl[static_cast<int64_t>(r0 + r) * inner], ov);
+                        else
+                            dl[static_cast<int64_t>(r0 + r) * inner] = ov;
                         const double od = static_cast<double>(ov);
                         rs[r] = fma(wkl, od, rs[r]);
                         if (MOM) {
@@ -919,9 +922,10 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
         // tiles run over the flattened line index
         const int L = tile_lines(n, sizeof(T));
         size_t lds = static_cast<size_t>(n) * L * sizeof(T);
-        // FP64 64-line tiles with the density: the tile is reused for the
-        // row sums (n rows of 17) and the moment partials (4 x 256 + 64)
-        if ((MODE == kFwdRho || MODE == kFwdRhoMom) && L == 64 && sizeof(T) == 8)
+        // 64-line tiles with the density evaluated by line groups: the tile
+        // is reused for the row sums (n rows of 17) and the moment partials
+        // (4 x 256 + 64)
+        if ((MODE == kFwdRho || MODE == kFwdRhoMom) && L == 64 && n % 16 == 0)
             lds = std::max(lds, (static_cast<size_t>(n) * 17 + 4 * kBlock + 64) * sizeof(double));
         if ((MODE == kFwdRho || MODE == kFwdRhoMom) &&
             (axis != 1 || (L != 64 && L != 32) || inner % L || n % (kBlock / L) ||

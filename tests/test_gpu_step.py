@@ -290,11 +290,13 @@ def test_run_with_every_step_formed_is_the_plain_step():
     ("spline", "f64", (12, 10, 16, 16)), ("spline", "f32", (12, 10, 16, 16)),
     ("spline", "f64", (6, 104, 16, 16)),     # 32-line tiles: two segments per wavefront
     ("spline", "f32", (4, 200, 8, 16)),
-    # FP64 64-line tiles, evaluated by line groups over n/16-row segments
+    # 64-line tiles, evaluated by line groups over n/16-row segments
     ("spline", "f64", (6, 16, 16, 16)), ("spline", "f64", (4, 96, 8, 16)),
     ("spline", "f64", (4, 48, 8, 16)),
-    # FP32 64-line tiles up to the longest line the tile holds
+    # FP32 64-line tiles up to the longest line the tile holds; lines that
+    # are no multiple of 16 points keep the per-line evaluation
     ("spline", "f32", (6, 48, 8, 16)), ("spline", "f32", (4, 192, 8, 16)),
+    ("spline", "f32", (4, 40, 8, 16)),
 ])
 def test_step_parity_with_density_from_the_x2_sweep(method, dt, dims):
     # the x2 sweep before each field solve also forms the density of its
