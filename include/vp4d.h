@@ -195,11 +195,15 @@ VP4D_API void vp_destroy(vp_state* st);
  *   W_trace  device, nsteps+1 doubles or NULL: W of f^m ... f^{m+nsteps}.
  *   moments  device, 4*(nsteps+1) doubles or NULL: mass, L1, L2, kinetic
  *            energy of the same states.
- * When N3*N4 is a multiple of 256 (SLDG) or of 64 with 64-line spline tiles
- * (N2 * 64 * sizeof(T) <= 48 KiB), the x2 sweep that precedes each field
- * solve also forms the density of its output, and the separate read of f
- * for rho is skipped; rho then differs from vp_density only in the order of
- * its FP64 additions.
+ * When the x2 sweep can form the density of its output, the x2 sweep that
+ * precedes each field solve (and the diagnostics) does so, and the separate
+ * read of f for rho is skipped; rho then differs from vp_density only in the
+ * order of its FP64 additions.  Conditions: SLDG, N3*N4 a multiple of 256
+ * and N2 <= 1532 (four wavefronts' partial sums in 48 KiB of LDS);
+ * spline, N3*N4 < 2^31 and a multiple of the tile width L (64 lines when
+ * N2 * 64 * sizeof(T) <= 48 KiB, else 32) with N2 a multiple of 256/L (and of
+ * 16 for FP64 64-line tiles); for both, per-workgroup partial sums of at
+ * most 1/16 of a state.
  */
 VP4D_API vp_status vp_strang_step(vp_state* st, void* f, void* f_tmp, int nsteps,
                          double tau, double* W_trace, double* moments,
