@@ -23,6 +23,7 @@
 // store element-parallel with contiguous global accesses.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "field.hpp"
 
@@ -213,6 +214,12 @@ enum { kFwd = 0, kAdj = 1, kDshift = 2, kFwdRho = 3, kFwdRhoMom = 4 };
 
 // Longest segment a thread owns: tiles hold at most kTileBytes, so a
 // segment has at most kTileBytes / (kBlock * sizeof(T)) points.
+// Tiles whose fused density evaluation runs by line groups: 64 lines, or 32
+// lines in FP64 (rows of at most 192 points), lines of a multiple of 16.
+__host__ __device__ constexpr bool line_group_tile(int L, int n, int esize) {
+    return (L == 64 || (L == 32 && esize == 8)) && n % 16 == 0;
+}
+
 template <typename T>
 struct SegMax {
     static constexpr int value = 48 * 1024 / (256 * static_cast<int>(sizeof(T)));
@@ -293,9 +300,8 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     constexpr bool FWD = MODE == kFwd || RHO;
     __shared__ double mred[MOM ? 4 * (kBlock / 64) : 1];
     double s_m = 0.0, s_a = 0.0, s_q = 0.0;   // W2 f, W2 |f|, W2 f^2 of this line
-    // 64-line tiles with the density (lines of a multiple of 16 points):
-    // each line's weights, shift, density weight and |v|^2, for the
-    // evaluation by line groups
+    // line-group tiles with the density: each line's weights, shift,
+    // density weight and |v|^2, for the evaluation by line groups
     constexpr bool LG = RHO;
     __shared__ T pw[LG ? 4 * 64 : 1];
     __shared__ int ps[LG ? 64 : 1];
@@ -375,7 +381,7 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         w2 = wq[2];
         w3 = wq[3];
     }
-    if (LG && L == 64 && n % 16 == 0 && threadIdx.x < 64) {
+    if (LG && line_group_tile(L, n, sizeof(T)) && static_cast<int>(threadIdx.x) < L) {
         // (the first segment's thread of every line; all 64 lines are whole)
         pw[4 * l] = w0;
         pw[4 * l + 1] = w1;
@@ -401,111 +407,120 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         return;
     }
     if constexpr (LG) {
-        if (L == 64 && n % 16 == 0) {
+        if (line_group_tile(L, n, sizeof(T))) {
             // Evaluation by (line group, row segment): a group of 16 lanes
             // (one row's 16 adjacent lines) makes the outputs of lines gi,
-            // gi+16, gi+32, gi+48 at the R = n/16 rows of one segment (R <= 6
-            // in FP64, 12 in FP32: a 64-line tile holds at most 96 / 192
-            // points a line), adding their weighted values per row in
-            // registers.
-            constexpr int kR = sizeof(T) == 8 ? 6 : 12;
-            const int gi = threadIdx.x & 15;
-            const int R = n / 16;
-            const int r0 = (static_cast<int>(threadIdx.x) >> 4) * R;
-            const double w2x = rf.g2.h;
-            T* __restrict__ tile = fout + o * n * inner + (kl - l);
-            double qm[4] = {0.0, 0.0, 0.0, 0.0};
-            double rs[kR];
+            // gi+16, .. (NC = L/16 of them) at the R = n/16 rows of one
+            // segment, adding their weighted values per row in registers.
+            // R <= kR: a 64-line tile holds at most 96 / 192 points a line in
+            // FP64 / FP32, a 32-line FP64 tile 192.  (Both shapes compiled
+            // with constant NC and kR.)
+            auto line_groups = [&](auto nc_c, auto kr_c) {
+                constexpr int NC = decltype(nc_c)::value;
+                constexpr int kR = decltype(kr_c)::value;
+                const int gi = threadIdx.x & 15;
+                const int R = n / 16;
+                const int r0 = (static_cast<int>(threadIdx.x) >> 4) * R;
+                const double w2x = rf.g2.h;
+                T* __restrict__ tile = fout + o * n * inner + (kl - l);
+                double qm[4] = {0.0, 0.0, 0.0, 0.0};
+                double rs[kR];
 #pragma unroll
-            for (int t = 0; t < kR; ++t) rs[t] = 0.0;
+                for (int t = 0; t < kR; ++t) rs[t] = 0.0;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int ln = gi + 16 * c;
-                const T a0 = pw[4 * ln], a1 = pw[4 * ln + 1];
-                const T a2 = pw[4 * ln + 2], a3 = pw[4 * ln + 3];
-                const double wkl = pwk[ln];
-                const double wm = wkl * w2x;
-                const double vv = MOM ? pvv[ln] : 0.0;
-                T* __restrict__ dl = tile + ln;
-                int j = first_tap(r0, ps[ln], n);
-                T c0 = buf[j * 64 + ln];
-                j = next_idx(j, n);
-                T c1 = buf[j * 64 + ln];
-                j = next_idx(j, n);
-                T c2 = buf[j * 64 + ln];
-                j = next_idx(j, n);
-                T c3 = buf[j * 64 + ln];
+                for (int c = 0; c < NC; ++c) {
+                    const int ln = gi + 16 * c;
+                    const T a0 = pw[4 * ln], a1 = pw[4 * ln + 1];
+                    const T a2 = pw[4 * ln + 2], a3 = pw[4 * ln + 3];
+                    const double wkl = pwk[ln];
+                    const double wm = wkl * w2x;
+                    const double vv = MOM ? pvv[ln] : 0.0;
+                    T* __restrict__ dl = tile + ln;
+                    int j = first_tap(r0, ps[ln], n);
+                    T c0 = buf[j * L + ln];
+                    j = next_idx(j, n);
+                    T c1 = buf[j * L + ln];
+                    j = next_idx(j, n);
+                    T c2 = buf[j * L + ln];
+                    j = next_idx(j, n);
+                    T c3 = buf[j * L + ln];
 #pragma unroll
-                for (int r = 0; r < kR; ++r) {
-                    if (r < R) {
-                        const T ov = fma(a3, c3, fma(a2, c2, fma(a1, c1, a0 * c0)));
-                        // (FP32: a group's 64-byte row pieces are half lines;
-                        // they stay cached to merge before write-back)
-                        if constexpr (sizeof(T) == 8)
-                            put_out(&dl[static_cast<int64_t>(r0 + r) * inner], ov);
-                        else
-                            dl[static_cast<int64_t>(r0 + r) * inner] = ov;
-                        const double od = static_cast<double>(ov);
-                        rs[r] = fma(wkl, od, rs[r]);
-                        if (MOM) {
-                            qm[0] = fma(wm, od, qm[0]);
-                            qm[1] = fma(wm, fabs(od), qm[1]);
-                            qm[2] = fma(wm * od, od, qm[2]);
-                            qm[3] = fma(wm * vv, od, qm[3]);
+                    for (int r = 0; r < kR; ++r) {
+                        if (r < R) {
+                            const T ov = fma(a3, c3, fma(a2, c2, fma(a1, c1, a0 * c0)));
+                            // (FP32: a group's 64-byte row pieces are half lines;
+                            // they stay cached to merge before write-back)
+                            if constexpr (sizeof(T) == 8)
+                                put_out(&dl[static_cast<int64_t>(r0 + r) * inner], ov);
+                            else
+                                dl[static_cast<int64_t>(r0 + r) * inner] = ov;
+                            const double od = static_cast<double>(ov);
+                            rs[r] = fma(wkl, od, rs[r]);
+                            if (MOM) {
+                                qm[0] = fma(wm, od, qm[0]);
+                                qm[1] = fma(wm, fabs(od), qm[1]);
+                                qm[2] = fma(wm * od, od, qm[2]);
+                                qm[3] = fma(wm * vv, od, qm[3]);
+                            }
+                            c0 = c1;
+                            c1 = c2;
+                            c2 = c3;
+                            j = next_idx(j, n);
+                            c3 = buf[j * L + ln];
                         }
-                        c0 = c1;
-                        c1 = c2;
-                        c2 = c3;
-                        j = next_idx(j, n);
-                        c3 = buf[j * 64 + ln];
                     }
                 }
-            }
-            // Sums through the (now free) tile, no cross-lane exchanges:
-            // thread (gi, p) puts its R row partials at
-            // red_rows[(p R + r) 17 + gi] (rows padded to 17 against bank
-            // conflicts) and, with the moments, its four moment partials at
-            // red_mom[q 256 + t].  After a barrier thread i < n adds the 16
-            // line groups of row i in order; the last wavefront (idle there,
-            // n <= 96) adds the moment partials in 64 strided chunks of 16,
-            // and after another barrier four threads add the chunks.
-            __syncthreads();
-            double* red_rows = reinterpret_cast<double*>(smem);
-            double* red_mom = red_rows + n * 17;      // [4][256]
-            double* red_chunk = red_mom + 4 * kBlock;  // [4][16]
+                // Sums through the (now free) tile, no cross-lane exchanges:
+                // thread (gi, p) puts its R row partials at
+                // red_rows[(p R + r) 17 + gi] (rows padded to 17 against bank
+                // conflicts) and, with the moments, its four moment partials at
+                // red_mom[q 256 + t].  After a barrier thread i < n adds the 16
+                // line groups of row i in order; the last wavefront (idle there:
+                // n <= 192) adds the moment partials in 64 strided chunks of 16,
+                // and after another barrier four threads add the chunks.
+                __syncthreads();
+                double* red_rows = reinterpret_cast<double*>(smem);
+                double* red_mom = red_rows + n * 17;      // [4][256]
+                double* red_chunk = red_mom + 4 * kBlock;  // [4][16]
 #pragma unroll
-            for (int r = 0; r < kR; ++r)
-                if (r < R) red_rows[(r0 + r) * 17 + gi] = rs[r];
-            if (MOM) {
-                const double w1x = rf.g1.h;
+                for (int r = 0; r < kR; ++r)
+                    if (r < R) red_rows[(r0 + r) * 17 + gi] = rs[r];
+                if (MOM) {
+                    const double w1x = rf.g1.h;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) red_mom[q * kBlock + threadIdx.x] = w1x * qm[q];
-            }
-            __syncthreads();
-            if (static_cast<int>(threadIdx.x) < n) {
-                const double* q = red_rows + threadIdx.x * 17;
-                double t = 0.0;
-#pragma unroll
-                for (int g = 0; g < 16; ++g) t += q[g];
-                rf.part[static_cast<int64_t>(blockIdx.x) * n + threadIdx.x] = t;
-            }
-            if (MOM) {
-                if (threadIdx.x >= kBlock - 64) {
-                    const int k = threadIdx.x - (kBlock - 64);
-                    const double* q = red_mom + (k >> 4) * kBlock + (k & 15);
-                    double t = 0.0;
-#pragma unroll
-                    for (int u = 0; u < kBlock / 16; ++u) t += q[16 * u];
-                    red_chunk[k] = t;
+                    for (int q = 0; q < 4; ++q) red_mom[q * kBlock + threadIdx.x] = w1x * qm[q];
                 }
                 __syncthreads();
-                if (threadIdx.x < 4) {
+                if (static_cast<int>(threadIdx.x) < n) {
+                    const double* q = red_rows + threadIdx.x * 17;
                     double t = 0.0;
 #pragma unroll
-                    for (int c = 0; c < 16; ++c) t += red_chunk[threadIdx.x * 16 + c];
-                    rf.mom_part[static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x] = t;
+                    for (int g = 0; g < 16; ++g) t += q[g];
+                    rf.part[static_cast<int64_t>(blockIdx.x) * n + threadIdx.x] = t;
                 }
-            }
+                if (MOM) {
+                    if (threadIdx.x >= kBlock - 64) {
+                        const int k = threadIdx.x - (kBlock - 64);
+                        const double* q = red_mom + (k >> 4) * kBlock + (k & 15);
+                        double t = 0.0;
+#pragma unroll
+                        for (int u = 0; u < kBlock / 16; ++u) t += q[16 * u];
+                        red_chunk[k] = t;
+                    }
+                    __syncthreads();
+                    if (threadIdx.x < 4) {
+                        double t = 0.0;
+#pragma unroll
+                        for (int c = 0; c < 16; ++c) t += red_chunk[threadIdx.x * 16 + c];
+                        rf.mom_part[static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x] = t;
+                    }
+                }
+            };
+            if (L == 64)
+                line_groups(std::integral_constant<int, 4>{},
+                            std::integral_constant<int, sizeof(T) == 8 ? 6 : 12>{});
+            else
+                line_groups(std::integral_constant<int, 2>{}, std::integral_constant<int, 12>{});
             return;
         }
     }
@@ -922,10 +937,10 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
         // tiles run over the flattened line index
         const int L = tile_lines(n, sizeof(T));
         size_t lds = static_cast<size_t>(n) * L * sizeof(T);
-        // 64-line tiles with the density evaluated by line groups: the tile
-        // is reused for the row sums (n rows of 17) and the moment partials
+        // tiles with the density evaluated by line groups: the tile is
+        // reused for the row sums (n rows of 17) and the moment partials
         // (4 x 256 + 64)
-        if ((MODE == kFwdRho || MODE == kFwdRhoMom) && L == 64 && n % 16 == 0)
+        if ((MODE == kFwdRho || MODE == kFwdRhoMom) && line_group_tile(L, n, sizeof(T)))
             lds = std::max(lds, (static_cast<size_t>(n) * 17 + 4 * kBlock + 64) * sizeof(double));
         if ((MODE == kFwdRho || MODE == kFwdRhoMom) &&
             (axis != 1 || (L != 64 && L != 32) || inner % L || n % (kBlock / L) ||

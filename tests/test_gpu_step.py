@@ -293,6 +293,8 @@ def test_run_with_every_step_formed_is_the_plain_step():
     # 64-line tiles, evaluated by line groups over n/16-row segments
     ("spline", "f64", (6, 16, 16, 16)), ("spline", "f64", (4, 96, 8, 16)),
     ("spline", "f64", (4, 48, 8, 16)),
+    # 32-line FP64 tiles by line groups (two lines a thread, up to 12 rows)
+    ("spline", "f64", (4, 112, 8, 16)), ("spline", "f64", (2, 192, 8, 16)),
     # FP32 64-line tiles up to the longest line the tile holds; lines that
     # are no multiple of 16 points keep the per-line evaluation
     ("spline", "f32", (6, 48, 8, 16)), ("spline", "f32", (4, 192, 8, 16)),
