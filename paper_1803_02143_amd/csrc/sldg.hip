@@ -428,11 +428,14 @@ sldg_row(const T* __restrict__ fin, T* __restrict__ fout,
          const double* __restrict__ shift, ShiftMap sm, int64_t nrows, int nc,
          int R, NodeBasis basis) {
     extern __shared__ __align__(16) unsigned char smem[];
-    T* ops = reinterpret_cast<T*>(smem);                   // R * 2 M^2
+    T* stage = reinterpret_cast<T*>(smem);                 // kBlock * M
+    T* ops = stage + kBlock * M;                           // R * 2 M^2
     int* sh = reinterpret_cast<int*>(ops + R * 2 * M * M);  // R
 
     const int64_t row0 = static_cast<int64_t>(blockIdx.x) * R;
     const int nr = static_cast<int>(min(static_cast<int64_t>(R), nrows - row0));
+    const int lane = threadIdx.x & 63;
+    T* wstage = stage + (threadIdx.x >> 6) * 64 * M;       // this wavefront's
 
     for (int r = threadIdx.x; r < nr; r += kBlock) {
         int s;
@@ -460,7 +463,10 @@ sldg_row(const T* __restrict__ fin, T* __restrict__ fout,
     const T* __restrict__ u0 = fin + row0 * N;
     T* __restrict__ o0 = fout + row0 * N;
     constexpr int kB = M <= 3 ? 4 : 2;
-    for (int q0 = threadIdx.x; q0 < ncell; q0 += kB * kBlock) {
+    // (the same trip count for every thread: the staging below needs whole
+    // wavefronts)
+    for (int base = 0; base < ncell; base += kB * kBlock) {
+        const int q0 = base + static_cast<int>(threadIdx.x);
         T ul[kB][M], ur[kB][M];
         int qq[kB];
 #pragma unroll
@@ -496,18 +502,21 @@ sldg_row(const T* __restrict__ fin, T* __restrict__ fout,
                 for (int l = 0; l < M; ++l) acc = fma(op[M * M + j * M + l], ur[b][l], acc);
                 out[j] = acc;
             }
-            if (q0 + b * kBlock < ncell) {
-                // (FP64: a lane's M-element run leaves every line partly
-                // written per store instruction; streamed, those partial
-                // lines cost extra write traffic, so FP64 rows stay cached)
+            // The wavefront's 64 cells are consecutive, so are their 64 M
+            // outputs: staged through the wavefront's LDS slice they leave
+            // as M whole-line stores instead of M stores of lane-strided
+            // runs.  (LDS operations of one wavefront execute in order; the
+            // wave barriers only keep the compiler from reordering them.)
 #pragma unroll
-                for (int j = 0; j < M; ++j) {
-                    if constexpr (sizeof(T) == 4)
-                        put_out(&o0[q * M + j], out[j]);
-                    else
-                        o0[q * M + j] = out[j];
-                }
+            for (int j = 0; j < M; ++j) wstage[lane * M + j] = out[j];
+            __builtin_amdgcn_wave_barrier();
+            const int64_t e0 = static_cast<int64_t>(q0 + b * kBlock - lane) * M;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const int64_t e = e0 + j * 64 + lane;
+                if (e < static_cast<int64_t>(ncell) * M) put_out(&o0[e], wstage[j * 64 + lane]);
             }
+            __builtin_amdgcn_wave_barrier();
         }
     }
 }
@@ -545,7 +554,7 @@ vp_status launch_sldg(int axis, const int64_t dims[4], const void* fin,
     int R = (M <= 3 ? 4 : 2) * 2 * kBlock / nc;
     if (R < 1) R = 1;
     if (R > kBlock) R = kBlock;
-    const size_t lds = R * per_row;
+    const size_t lds = static_cast<size_t>(kBlock) * M * sizeof(T) + R * per_row;
     const unsigned grid = blocks_for(outer, R);
     sldg_row<M, T, ADJ><<<grid, kBlock, lds, st>>>(in, out, shift, sm, outer, nc, R, b);
     return check_launch("sldg_row");
