@@ -50,17 +50,18 @@ def projection_matrices(degree, alpha):
 def split_shift(sigma):
     """n = floor(sigma) (a Python int) and alpha = sigma - n, both from FP64.
 
-    A shift a rounding step below an integer can give alpha = 1 exactly; it
-    is then taken as (n + 1, 0), the same point of the line (A(1) = I = B(0)
-    shifted by one cell), so that one-sided shift derivatives are always
-    taken from the right.
+    This is the exact floor branch: the translated point lies in the cell
+    that sigma itself falls in.  For sigma in [-2^-54, 0) the difference
+    sigma - floor(sigma) = 1 + sigma rounds to 1.0, so alpha may equal one.
+    The forward map is unaffected (A(1) = I, B(1) = 0 shifted by one cell is
+    A(0) = 0, B(0) = I), but a shift derivative taken here is the derivative
+    at sigma, i.e. the one from the left of the whole cell, not from the
+    right.  Only an exactly integer sigma gives alpha = 0 and the one-sided
+    derivative from the right.
     """
     sigma = float(sigma)
     n = np.floor(sigma)
     alpha = sigma - n
-    if alpha >= 1.0:
-        n += 1.0
-        alpha = 0.0
     return int(n), alpha
 
 

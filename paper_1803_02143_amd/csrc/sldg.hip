@@ -127,7 +127,7 @@ __device__ __forceinline__ void sldg_operator_deriv(const NodeBasis& b, double s
                                                     int nc, int& s, T dA[M][M],
                                                     T dB[M][M]) {
     double alpha;
-    const bool ok = split_shift(sigma, nc, s, alpha);
+    const bool ok = split_shift_floor(sigma, nc, s, alpha);
     const double beta = 1.0 - alpha;
     double la[M], l1[M], l0[M];
     lagrange_all<M>(b, alpha, la);

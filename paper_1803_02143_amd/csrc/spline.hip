@@ -229,7 +229,7 @@ struct SegMax {
 template <typename T>
 __device__ __forceinline__ void spline_dweights(double sigma, int n, int& s, T wq[4]) {
     double alpha;
-    const bool ok = split_shift(sigma, n, s, alpha);
+    const bool ok = split_shift_floor(sigma, n, s, alpha);
     const double t = 1.0 - alpha;
     const double g = -6.0 * (1.7320508075688772 - 2.0) / 6.0;  // -6r/6
     // 6 d beta_q / dt; d/d alpha = -d/dt

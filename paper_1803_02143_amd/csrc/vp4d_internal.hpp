@@ -117,6 +117,27 @@ __device__ __forceinline__ bool split_shift(double sigma, int n, int& s,
     return true;
 }
 
+// The split for shift derivatives: the exact floor branch.  For sigma in
+// [-2^-54, 0) the fraction sigma - floor(sigma) = 1 + sigma rounds to one;
+// the forward sweeps move that case to (s + 1, 0), the same output, but a
+// derivative must be taken in the cell that holds sigma, so here s stays
+// floor(sigma) mod n and alpha = 1 (the derivative from the left of the
+// whole cell).  Only an exactly integer sigma gives alpha = 0.
+__device__ __forceinline__ bool split_shift_floor(double sigma, int n, int& s,
+                                                  double& alpha) {
+    if (!(fabs(sigma) < 4.0e18)) {
+        s = 0;
+        alpha = 0.0;
+        return false;
+    }
+    const double fl = floor(sigma);
+    alpha = sigma - fl;
+    long long q = static_cast<long long>(fl) % static_cast<long long>(n);
+    if (q < 0) q += n;
+    s = static_cast<int>(q);
+    return true;
+}
+
 // v from lane (lane ^ m), m a power of two known at compile time after
 // unrolling: within a quad by DPP quad permutations, up to 16 by the
 // swizzle crossbar (bit mode: and 0x1F, xor m), 32 by a lane permute.

@@ -168,3 +168,49 @@ def test_final_energy_gradient_matches_central_differences(method):
     g_d = np.sum(grad * d)
     fd = (J(f0(0.5) + h * d) - J(f0(0.5) - h * d)) / (2 * h)
     assert _rel(g_d, fd) < 1e-6, (g_d, fd)
+
+
+@pytest.mark.parametrize("method,degree", [("sldg", 1), ("sldg", 2), ("sldg", 3), ("spline", None)])
+def test_shift_derivative_just_below_zero_is_the_left_one(method, degree):
+    # For sigma in (-1, 0) the floor is -1 and the line map is a polynomial
+    # in sigma (degree 2l+1 in alpha for SLDG, 3 for the spline), so the
+    # derivative at sigma = -1e-17 is fixed by samples inside (-1, 0): an
+    # exact fit differentiated at -1e-17, and a one-sided difference below
+    # zero.
+    m = 1 if method == "spline" else degree + 1
+    n_pts = 7 * m
+    rng = np.random.default_rng(21)
+    u = rng.uniform(-1.0, 1.0, size=(3, n_pts))
+    lam = rng.uniform(-1.0, 1.0, size=(3, n_pts))
+    if method == "sldg":
+        fwd = lambda s: np.sum(sldg.sweep(u, 1, np.full((3, 1), s), degree) * lam, axis=1)  # noqa: E731
+        dshift = lambda s: adjoint.sldg_sweep_dshift(u, lam, 1, np.full((3, 1), s), degree)  # noqa: E731
+        pdeg = 2 * degree + 1
+    else:
+        fwd = lambda s: np.sum(spline.sweep(u, 1, np.full((3, 1), s)) * lam, axis=1)  # noqa: E731
+        dshift = lambda s: adjoint.spline_sweep_dshift(u, lam, 1, np.full((3, 1), s))  # noqa: E731
+        pdeg = 3
+    s0 = -1e-17
+    n, alpha = sldg.split_shift(s0)
+    assert n == -1 and alpha == 1.0
+    got = dshift(s0)
+    # exact: polynomial through pdeg+3 points of (-1, 0), differentiated at s0
+    xs = -np.linspace(0.05, 0.95, pdeg + 3)
+    ys = np.array([fwd(x) for x in xs])
+    for r in range(3):
+        p = np.polynomial.Polynomial.fit(xs, ys[:, r], pdeg)
+        assert abs(p.deriv()(s0) - got[r]) < 1e-9 * max(1.0, abs(got[r]))
+    # one-sided difference below zero (second order: from -h and -2h)
+    h = 1e-5
+    fd = (3 * fwd(s0) - 4 * fwd(s0 - h) + fwd(s0 - 2 * h)) / (2 * h)
+    np.testing.assert_allclose(got, fd, rtol=1e-7, atol=1e-7)
+    # SLDG: the right derivative at zero is another number (the projected
+    # map has a kink at whole cells); spline: the cubic B-spline has a
+    # continuous first derivative, so both sides agree
+    right = dshift(0.0)
+    if method == "sldg":
+        assert np.max(np.abs(right - got)) > 1e-3 * np.max(np.abs(got))
+    else:
+        np.testing.assert_allclose(right, got, rtol=1e-13, atol=1e-13)
+    # the forward map is continuous across zero: bitwise the same lines
+    assert np.array_equal(fwd(s0), fwd(0.0))

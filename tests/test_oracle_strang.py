@@ -5,7 +5,7 @@ import math
 
 import numpy as np
 import pytest
-from scipy.special import wofz
+from scipy.special import erf, wofz
 
 from oracle import field, strang
 from vp_inputs import workload
@@ -169,3 +169,36 @@ def test_two_stream_product_form_matches_paper():
     gv = math.exp(-0.5 * (v - 2.4) ** 2) + math.exp(-0.5 * (v + 2.4) ** 2)
     ref = (1 + 1e-3 * math.cos(0.2 * x) ** 2) * gv * gv / (8 * math.pi)
     assert abs(f[0, 0, 0, 0] - ref) < 1e-16
+
+
+def test_two_stream_sum_form_point_value_and_mass():
+    # The two-stream workloads use the sum perturbation 1 + eps (cos k x1 +
+    # cos k x2) on v in [-9, 9) (Sec. 5, Eq. (7) with the sum in place of the
+    # product).  Point value: x nodes at (i + 1/2) L / 3, where k x = pi/3
+    # for i = 0 (cos = 1/2, so the sum form gives 1 + eps and the product
+    # form 1 + eps/4).
+    w = workload("two_stream_64")
+    assert w.form == "sum" and w.lo[2] == -9.0 and w.length[2] == 18.0
+    dims = (3, 3, 2, 2)
+    f = field.initial_condition("two_stream", dims, w.lo, w.length, None, w.eps, w.k, w.v0)
+    v = -9.0 + 18.0 / 4
+    gv = math.exp(-0.5 * (v - 2.4) ** 2) + math.exp(-0.5 * (v + 2.4) ** 2)
+    ref = (1.0 + 1e-3 * (0.5 + 0.5)) * gv * gv / (8.0 * math.pi)
+    assert abs(f[0, 0, 0, 0] - ref) < 1e-16
+    # i = 1: k x = pi, cos = -1 for both axes
+    ref11 = (1.0 - 2e-3) * gv * gv / (8.0 * math.pi)
+    assert abs(f[1, 1, 1, 1] - ref11) < 1e-16
+    # Mass: the x integral of the perturbation vanishes over whole periods
+    # (k L = 2 pi), each velocity factor integrates to
+    # sqrt(pi/2) [erf((9 - v0)/sqrt 2) + erf((9 + v0)/sqrt 2)] per bump, so
+    # mass = L1 L2 / (8 pi) G^2 with G = 2 sqrt(pi/2)[...].  The midpoint
+    # rule of the spline grid is spectrally accurate for the bumps.
+    n = 48
+    f = field.initial_condition("two_stream", (8, 8, n, n), w.lo, w.length, None,
+                                w.eps, w.k, w.v0)
+    mass, l1, _, _ = field.moments(f, None, w.lo, w.length)
+    s2 = math.sqrt(2.0)
+    G = 2.0 * math.sqrt(math.pi / 2.0) * (erf((9.0 - 2.4) / s2) + erf((9.0 + 2.4) / s2))
+    exact = w.length[0] * w.length[1] / (8.0 * math.pi) * G * G
+    assert abs(mass - exact) < 1e-10 * exact
+    assert abs(l1 - mass) < 1e-14 * mass
