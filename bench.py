@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--no-merged", action="store_true",
                     help="skip the timing of runs with merged x half-steps")
     ap.add_argument("--diag-every", type=int, default=10)
+    ap.add_argument("--no-two-stream", action="store_true",
+                    help="skip the two-stream legs (192^4 FP64 and FP32, 288^4 FP32)")
+    ap.add_argument("--two-stream-steps", type=int, default=10,
+                    help="timed Strang steps of each two-stream leg at 192^4 (half at 288^4)")
     ap.add_argument("--copy-ref", type=int, default=0,
                     help="plain device copies of one f buffer before the run (a "
                          "reference kernel of known size for hardware counters)")
@@ -82,6 +86,24 @@ def counter_traffic(kernel_key, workload_name, dtype):
     return None
 
 
+def host_info():
+    """CPU model and the number of host cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"cpu_model": model, "nproc": usable, "os_cpu_count": os.cpu_count()}
+
+
 def cpu_baseline(w, dtype):
     """The oracle's sweep rate on a bounded sample: one SLDG and one spline
     sweep along every axis of the full grid, shifts of the step's shape."""
@@ -111,7 +133,7 @@ def cpu_baseline(w, dtype):
             updates += 2 * int(np.prod(dims))
     dt = time.perf_counter() - t0
     return {"value": updates / dt, "unit": "dof-updates/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "host": host_info(),
             "sample": f"one SLDG (degree {w.degree}) and one cubic-spline sweep along "
                       f"each of the 4 axes of the full {'x'.join(map(str, dims))} grid, "
                       f"float64, 1 thread, {dt:.1f} s"}
@@ -164,6 +186,74 @@ def run_precision(vp, torch, w, dt, methods, steps, warmup, stream, copy_ref=0):
         r["st"].close()
         del r["tmp"]
     return elapsed, runs
+
+
+def two_stream_legs(vp, torch, methods, steps, stream):
+    """The two-stream workloads at one GPU: 192^4 dofs (64^4 cells, degree 2)
+    in FP64 and FP32, with the difference of the FP32 run from the FP64 one
+    after the timed steps, and 288^4 dofs (96^4 cells) in FP32.  Per leg:
+    ms per Strang step and dof-updates/s per method, and every sweep kernel's
+    average launch time and algorithmic rate from the library's HIP events."""
+    import numpy as np
+
+    from vp_inputs import workload
+
+    out = {}
+    w = workload("two_stream_64")
+    n4 = int(np.prod(w.dofs))
+    leg = {"dofs": list(w.dofs), "steps": steps, "warmup": 2, "dt": w.dt}
+    keep = {}
+    for dt in ("f64", "f32"):
+        esize = 8 if dt == "f64" else 4
+        elapsed, runs = run_precision(vp, torch, w, dt, methods, steps, 2, stream)
+        detail, dominant = kernel_table(runs, n4, esize)
+        leg[dt] = {
+            "ms_per_step": elapsed / steps * 1e3,
+            "dof_updates_per_s": SWEEPS_PER_STEP * len(runs) * n4 * steps / elapsed,
+            "ms_per_step_by_method": {r["name"]: r["ms_per_step"] for r in runs},
+            "kernels": detail, "dominant": dominant,
+            "dominant_frac_of_peak": detail[dominant]["alg_GBs"] / HBM_PEAK_GBS,
+        }
+        keep[dt] = runs
+    diffs = {}
+    for r, q in zip(keep["f64"], keep["f32"]):
+        fa = r["f"]
+        num = 0.0
+        den = 0.0
+        for a0 in range(0, fa.shape[0], 16):        # in slabs: no full FP64 temporaries
+            x = fa[a0:a0 + 16]
+            y = q["f"][a0:a0 + 16].double()
+            num += float(((y - x) ** 2).sum())
+            den += float((x ** 2).sum())
+        diffs[r["name"]] = {
+            "rel_l2_f": math.sqrt(num / den),
+            "rel_max_W": float(((q["W"] - r["W"]).abs() / r["W"].abs()).max()),
+            "W_el_last_f64": float(r["W"][-1].item()),
+        }
+    leg["f32_vs_f64_after_run"] = diffs
+    leg["f32_speedup_vs_f64"] = leg["f64"]["ms_per_step"] / leg["f32"]["ms_per_step"]
+    del keep, runs, r, q
+    torch.cuda.empty_cache()
+    out[w.name] = leg
+
+    w = workload("two_stream_96")
+    n4 = int(np.prod(w.dofs))
+    st = max(1, steps // 2)
+    elapsed, runs = run_precision(vp, torch, w, "f32", methods, st, 1, stream)
+    detail, dominant = kernel_table(runs, n4, 4)
+    out[w.name] = {
+        "dofs": list(w.dofs), "dtype": "f32", "steps": st, "warmup": 1, "dt": w.dt,
+        "ms_per_step": elapsed / st * 1e3,
+        "dof_updates_per_s": SWEEPS_PER_STEP * len(runs) * n4 * st / elapsed,
+        "ms_per_step_by_method": {r["name"]: r["ms_per_step"] for r in runs},
+        "kernels": detail, "dominant": dominant,
+        "dominant_frac_of_peak": detail[dominant]["alg_GBs"] / HBM_PEAK_GBS,
+        "rel_mass_drift": {r["name"]: float(((r["mom"][0::4] - r["mom"][0]).abs().max()
+                                             / r["mom"][0]).item()) for r in runs},
+    }
+    del runs
+    torch.cuda.empty_cache()
+    return out
 
 
 def _event_ms(torch, stream, fn, reps):
@@ -490,6 +580,8 @@ def main():
             "kernels": {k: {kk: v[kk] for kk in ("avg_ms", "dof_updates_per_s", "alg_GBs") if kk in v}
                         for k, v in odetail.items()},
         }
+    if not a.no_two_stream:
+        out["two_stream"] = two_stream_legs(vp, torch, methods, a.two_stream_steps, stream)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, dt)
     print(json.dumps(out))

@@ -93,9 +93,11 @@ VP4D_API vp_status sldg_advect(int axis, int degree, vp_dtype dt, const int64_t 
  * periodic tridiagonal system (1/6)(omega_{i-1} + 4 omega_i + omega_{i+1}) =
  * u_i, and the spline is evaluated at x_i - sigma*h.  sigma is in grid
  * points.  The coefficients omega stay on chip and are never written to
- * memory.  Arguments as for sldg_advect (no degree; any dims[axis] >= 1).
+ * memory.  Arguments as for sldg_advect (any dims[axis] >= 1), except
+ *   degree        the spline degree: must be 3 (the cubic B-spline of Sec. 3);
+ *                 any other value is VP_ERR_UNSUPPORTED.
  */
-VP4D_API vp_status spline_advect(int axis, vp_dtype dt, const int64_t dims[4],
+VP4D_API vp_status spline_advect(int axis, int degree, vp_dtype dt, const int64_t dims[4],
                         const void* f_in, void* f_out, const double* shift,
                         const int64_t shift_stride[4], void* stream);
 
@@ -260,14 +262,16 @@ VP4D_API vp_status sldg_advect_dshift(int axis, int degree, vp_dtype dt,
                              double* g_line, void* stream);
 
 /* spline_advect_adjoint -- transpose of spline_advect for fixed shifts,
- * C^{-1} E(alpha)^T lam_out (C is symmetric).  As sldg_advect_adjoint. */
-VP4D_API vp_status spline_advect_adjoint(int axis, vp_dtype dt, const int64_t dims[4],
+ * C^{-1} E(alpha)^T lam_out (C is symmetric).  As sldg_advect_adjoint;
+ * degree must be 3. */
+VP4D_API vp_status spline_advect_adjoint(int axis, int degree, vp_dtype dt, const int64_t dims[4],
                                 const void* lam_out, void* lam_in, const double* shift,
                                 const int64_t shift_stride[4], void* stream);
 
 /* spline_advect_dshift -- per-line derivative of <lam_out, spline_advect(f_in)>
- * with respect to the shift (derivative of the B-spline weights). */
-VP4D_API vp_status spline_advect_dshift(int axis, vp_dtype dt, const int64_t dims[4],
+ * with respect to the shift (derivative of the B-spline weights); degree
+ * must be 3. */
+VP4D_API vp_status spline_advect_dshift(int axis, int degree, vp_dtype dt, const int64_t dims[4],
                                const void* f_in, const void* lam_out, const double* shift,
                                const int64_t shift_stride[4], double* g_line,
                                void* stream);

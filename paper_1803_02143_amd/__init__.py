@@ -107,15 +107,15 @@ def sldg_advect(axis, degree, f_in, f_out, shift, shift_stride=None, stream=None
         _stream(stream)))
 
 
-def spline_advect(axis, f_in, f_out, shift, shift_stride=None, stream=None):
-    """One periodic cubic-spline sweep (C ABI ``spline_advect``)."""
+def spline_advect(axis, f_in, f_out, shift, shift_stride=None, stream=None, degree=3):
+    """One periodic cubic-spline sweep (C ABI ``spline_advect``; degree 3 only)."""
     if shift_stride is None:
         shift_stride = broadcast_strides(shift, axis)
     if f_in.dtype != f_out.dtype or f_in.shape != f_out.shape:
         raise ValueError("f_in and f_out must match in shape and dtype")
     _check_shift(shift, f_in.shape, axis, shift_stride)
     _check("spline_advect", lib().spline_advect(
-        int(axis), _dtype(f_in), _dims(f_in), _dev(f_in, "f_in"), _dev(f_out, "f_out"),
+        int(axis), int(degree), _dtype(f_in), _dims(f_in), _dev(f_in, "f_in"), _dev(f_out, "f_out"),
         _f64(shift, "shift"), _lib.i64x4(shift_stride), _stream(stream)))
 
 
@@ -150,7 +150,8 @@ def sldg_advect_dshift(axis, degree, f_in, lam_out, shift, g_line, shift_stride=
         _f64(g_line, "g_line", _lines_numel(f_in, axis)), _stream(stream)))
 
 
-def spline_advect_adjoint(axis, lam_out, lam_in, shift, shift_stride=None, stream=None):
+def spline_advect_adjoint(axis, lam_out, lam_in, shift, shift_stride=None, stream=None,
+                          degree=3):
     """Transpose of the spline sweep for fixed shifts (C ABI ``spline_advect_adjoint``)."""
     if shift_stride is None:
         shift_stride = broadcast_strides(shift, axis)
@@ -158,12 +159,13 @@ def spline_advect_adjoint(axis, lam_out, lam_in, shift, shift_stride=None, strea
         raise ValueError("lam_out and lam_in must match in shape and dtype")
     _check_shift(shift, lam_out.shape, axis, shift_stride)
     _check("spline_advect_adjoint", lib().spline_advect_adjoint(
-        int(axis), _dtype(lam_out), _dims(lam_out), _dev(lam_out, "lam_out"),
+        int(axis), int(degree), _dtype(lam_out), _dims(lam_out), _dev(lam_out, "lam_out"),
         _dev(lam_in, "lam_in"), _f64(shift, "shift"), _lib.i64x4(shift_stride),
         _stream(stream)))
 
 
-def spline_advect_dshift(axis, f_in, lam_out, shift, g_line, shift_stride=None, stream=None):
+def spline_advect_dshift(axis, f_in, lam_out, shift, g_line, shift_stride=None, stream=None,
+                         degree=3):
     """Per-line d<lam_out, spline sweep(f_in)>/d shift (C ABI ``spline_advect_dshift``)."""
     if shift_stride is None:
         shift_stride = broadcast_strides(shift, axis)
@@ -171,7 +173,7 @@ def spline_advect_dshift(axis, f_in, lam_out, shift, g_line, shift_stride=None, 
         raise ValueError("f_in and lam_out must match in shape and dtype")
     _check_shift(shift, f_in.shape, axis, shift_stride)
     _check("spline_advect_dshift", lib().spline_advect_dshift(
-        int(axis), _dtype(f_in), _dims(f_in), _dev(f_in, "f_in"), _dev(lam_out, "lam_out"),
+        int(axis), int(degree), _dtype(f_in), _dims(f_in), _dev(f_in, "f_in"), _dev(lam_out, "lam_out"),
         _f64(shift, "shift"), _lib.i64x4(shift_stride),
         _f64(g_line, "g_line", _lines_numel(f_in, axis)), _stream(stream)))
 

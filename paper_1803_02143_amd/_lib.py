@@ -34,8 +34,8 @@ _dp = ctypes.c_void_p          # device double*, passed as an address
 SIGNATURES = {
     "sldg_advect": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64x4,
                                    _vp, _vp, _dp, _i64x4, _vp]),
-    "spline_advect": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64x4, _vp, _vp,
-                                     _dp, _i64x4, _vp]),
+    "spline_advect": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64x4,
+                                     _vp, _vp, _dp, _i64x4, _vp]),
     "vp_density": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64x4, _vp,
                                   ctypes.c_double, ctypes.c_double, _dp, _vp]),
     "vp_poisson": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
@@ -60,10 +60,10 @@ SIGNATURES = {
                                            _vp, _vp, _dp, _i64x4, _vp]),
     "sldg_advect_dshift": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64x4,
                                           _vp, _vp, _dp, _i64x4, _dp, _vp]),
-    "spline_advect_adjoint": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64x4, _vp, _vp,
-                                             _dp, _i64x4, _vp]),
-    "spline_advect_dshift": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64x4, _vp, _vp,
-                                            _dp, _i64x4, _dp, _vp]),
+    "spline_advect_adjoint": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             _i64x4, _vp, _vp, _dp, _i64x4, _vp]),
+    "spline_advect_dshift": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            _i64x4, _vp, _vp, _dp, _i64x4, _dp, _vp]),
     "vp_density_adjoint": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64x4, _dp,
                                           ctypes.c_double, ctypes.c_double, _vp, ctypes.c_int,
                                           _vp]),

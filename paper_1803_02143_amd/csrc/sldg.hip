@@ -505,18 +505,25 @@ sldg_row(const T* __restrict__ fin, T* __restrict__ fout,
             // The wavefront's 64 cells are consecutive, so are their 64 M
             // outputs: staged through the wavefront's LDS slice they leave
             // as M whole-line stores instead of M stores of lane-strided
-            // runs.  (LDS operations of one wavefront execute in order; the
-            // wave barriers only keep the compiler from reordering them.)
+            // runs.  The lanes exchange values through the slice, so each
+            // wave barrier sits between a release and an acquire fence of
+            // wavefront scope: the writes of every lane are visible to the
+            // reads of the others (and the next round's writes wait for
+            // this round's reads).  On LDS these fences cost nothing.
 #pragma unroll
             for (int j = 0; j < M; ++j) wstage[lane * M + j] = out[j];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             const int64_t e0 = static_cast<int64_t>(q0 + b * kBlock - lane) * M;
 #pragma unroll
             for (int j = 0; j < M; ++j) {
                 const int64_t e = e0 + j * 64 + lane;
                 if (e < static_cast<int64_t>(ncell) * M) put_out(&o0[e], wstage[j * 64 + lane]);
             }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
 }

@@ -1064,12 +1064,15 @@ vp_status check_spline_args(int axis, vp_dtype dt, const int64_t dims[4], const 
 
 }  // namespace
 
-extern "C" vp_status spline_advect(int axis, vp_dtype dt, const int64_t dims[4],
+extern "C" vp_status spline_advect(int axis, int degree, vp_dtype dt, const int64_t dims[4],
                                    const void* f_in, void* f_out,
                                    const double* shift,
                                    const int64_t shift_stride[4], void* stream) {
     using namespace vp;
     clear_error();
+    if (degree != 3)
+        return set_error(VP_ERR_UNSUPPORTED, "spline degree %d: only the cubic spline (3)",
+                         degree);
     int64_t total = 0;
     vp_status rc = check_spline_args(axis, dt, dims, f_in, f_out, shift, shift_stride, &total);
     if (rc != VP_OK) return rc;
@@ -1079,12 +1082,15 @@ extern "C" vp_status spline_advect(int axis, vp_dtype dt, const int64_t dims[4],
                               static_cast<hipStream_t>(stream), false);
 }
 
-extern "C" vp_status spline_advect_adjoint(int axis, vp_dtype dt, const int64_t dims[4],
+extern "C" vp_status spline_advect_adjoint(int axis, int degree, vp_dtype dt, const int64_t dims[4],
                                            const void* lam_out, void* lam_in,
                                            const double* shift,
                                            const int64_t shift_stride[4], void* stream) {
     using namespace vp;
     clear_error();
+    if (degree != 3)
+        return set_error(VP_ERR_UNSUPPORTED, "spline degree %d: only the cubic spline (3)",
+                         degree);
     int64_t total = 0;
     vp_status rc = check_spline_args(axis, dt, dims, lam_out, lam_in, shift, shift_stride,
                                      &total);
@@ -1095,13 +1101,16 @@ extern "C" vp_status spline_advect_adjoint(int axis, vp_dtype dt, const int64_t 
                               static_cast<hipStream_t>(stream), true);
 }
 
-extern "C" vp_status spline_advect_dshift(int axis, vp_dtype dt, const int64_t dims[4],
+extern "C" vp_status spline_advect_dshift(int axis, int degree, vp_dtype dt, const int64_t dims[4],
                                           const void* f_in, const void* lam_out,
                                           const double* shift,
                                           const int64_t shift_stride[4], double* g_line,
                                           void* stream) {
     using namespace vp;
     clear_error();
+    if (degree != 3)
+        return set_error(VP_ERR_UNSUPPORTED, "spline degree %d: only the cubic spline (3)",
+                         degree);
     int64_t total = 0;
     vp_status rc = check_spline_args(axis, dt, dims, f_in, lam_out, shift, shift_stride, &total);
     if (rc != VP_OK) return rc;

@@ -77,8 +77,16 @@ def test_spline_and_field_argument_errors():
     st = L.i64x4((0, 0, 1, 0))
     a, b = _fake(), _fake()
     pa, pb = (ctypes.cast(x, ctypes.c_void_p) for x in (a, b))
-    assert lib.spline_advect(-1, L.VP_F32, dims, pa, pb, pa, st, None) == L.VP_ERR_ARG
-    assert lib.spline_advect(0, L.VP_F32, dims, pa, pa, pb, st, None) == L.VP_ERR_ALIAS
+    assert lib.spline_advect(-1, 3, L.VP_F32, dims, pa, pb, pa, st, None) == L.VP_ERR_ARG
+    assert lib.spline_advect(0, 3, L.VP_F32, dims, pa, pa, pb, st, None) == L.VP_ERR_ALIAS
+    for deg in (2, 1, 5, -1):
+        assert lib.spline_advect(0, deg, L.VP_F32, dims, pa, pb, pa, st, None) == \
+            L.VP_ERR_UNSUPPORTED
+        assert "cubic" in lib.vp_last_error().decode()
+        assert lib.spline_advect_adjoint(0, deg, L.VP_F32, dims, pa, pb, pa, st, None) == \
+            L.VP_ERR_UNSUPPORTED
+        assert lib.spline_advect_dshift(0, deg, L.VP_F32, dims, pa, pb, pa, st, pb, None) == \
+            L.VP_ERR_UNSUPPORTED
     assert lib.vp_density(-2, L.VP_F64, dims, pa, 1.0, 1.0, pb, None) == L.VP_ERR_UNSUPPORTED
     assert lib.vp_density(2, L.VP_F64, dims, pa, -1.0, 1.0, pb, None) == L.VP_ERR_ARG
     ws = lib.vp_poisson_workspace(2, 6, 6)
@@ -110,8 +118,8 @@ def test_adjoint_and_run_argument_errors():
     assert lib.sldg_advect_adjoint(5, 2, L.VP_F64, dims, pa, pb, ps, st, None) == L.VP_ERR_ARG
     assert lib.sldg_advect_adjoint(0, 2, L.VP_F64, dims, pa, pa, ps, st, None) == L.VP_ERR_ALIAS
     assert lib.sldg_advect_dshift(0, 2, L.VP_F64, dims, pa, pb, ps, st, None, None) == L.VP_ERR_ARG
-    assert lib.spline_advect_adjoint(0, L.VP_F64, dims, pa, pa, ps, st, None) == L.VP_ERR_ALIAS
-    assert lib.spline_advect_dshift(0, 7, dims, pa, pb, ps, st, pg, None) == L.VP_ERR_ARG
+    assert lib.spline_advect_adjoint(0, 3, L.VP_F64, dims, pa, pa, ps, st, None) == L.VP_ERR_ALIAS
+    assert lib.spline_advect_dshift(0, 3, 7, dims, pa, pb, ps, st, pg, None) == L.VP_ERR_ARG
     assert lib.vp_density_adjoint(2, L.VP_F64, dims, None, 1.0, 1.0, pa, 0, None) == L.VP_ERR_ARG
     assert lib.vp_density_adjoint(2, L.VP_F64, dims, pb, 0.0, 1.0, pa, 0, None) == L.VP_ERR_ARG
     ws = lib.vp_poisson_workspace(2, 6, 6)

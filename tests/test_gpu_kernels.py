@@ -7,7 +7,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_common import (announce, assert_close, rel_l2, require_gpu, to_dev,
+from gpu_common import (announce, assert_close, rel_l2, rel_max, require_gpu, to_dev,
                         to_host, torch)
 from oracle import field, sldg, spline
 from vp_inputs import random_field, random_shifts
@@ -168,6 +168,40 @@ def test_nonfinite_shift_gives_nan_line_only():
     mask[1, 2, :, 3] = False
     mask[4, 0, :, 5] = False
     assert np.array_equal(got[mask], f[mask])
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("axis", [0, 2, 3])
+def test_spline_nonfinite_shift_gives_nan_line_only(dt, axis):
+    # strided (column tile) and contiguous (row tile) lines: a NaN or an
+    # infinite shift poisons its own line and leaves the others of the tile
+    vp = require_gpu()
+    dims = (8, 6, 10, 12)
+    f = random_field(dims, seed=2)
+    fin = to_dev(f, dt)
+    fr = to_host(fin)
+    shape = list(dims)
+    shape[axis] = 1
+    sig = np.random.default_rng(3).uniform(-2.0, 2.0, size=shape)
+    bad = [(1, 2, 0, 3), (4, 0, 5, 7)]
+    for b, v in zip(bad, (np.nan, -np.inf)):
+        idx = list(b)
+        idx[axis] = 0
+        sig[tuple(idx)] = v
+    announce(f"spline non-finite shifts {dt} axis={axis}")
+    out = torch.empty_like(fin)
+    vp.spline_advect(axis, fin, out, to_dev(sig))
+    got = to_host(out)
+    mask = np.ones(dims, bool)
+    for b in bad:
+        sl = list(b)
+        sl[axis] = slice(None)
+        assert np.all(np.isnan(got[tuple(sl)])), b
+        mask[tuple(sl)] = False
+    assert np.all(np.isfinite(got[mask]))
+    ref = spline.sweep(fr, axis, np.where(np.isfinite(sig), sig, 0.0))
+    tol = 1e-12 if dt == "f64" else 2e-6
+    assert rel_max(got[mask], ref[mask]) < tol
 
 
 # --------------------------------------------------------- field kernels ---
