@@ -135,6 +135,26 @@ VP4D_API vp_status vp_poisson(int degree, int64_t n1, int64_t n2, double L1, dou
 VP4D_API size_t vp_poisson_workspace(int degree, int64_t n1, int64_t n2);
 
 /*
+ * vp_poisson_noalloc -- vp_poisson for callers that cannot allocate device
+ * memory or pass a workspace: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, result and
+ * kernels as vp_poisson, without the workspace: the library keeps a static
+ * device array of 12.6 MB on every device it runs on (held until the
+ * process ends) and the call allocates nothing.
+ *
+ *   n1 * n2  at most VP_POISSON_NOALLOC_MAX_POINTS; a larger grid is
+ *            VP_ERR_WORKSPACE (use vp_poisson with a workspace).
+ * Every call on one device uses that device's array, which keeps the last
+ * call's contents (nothing in it needs to start at zero).  Calls that
+ * overlap in time on one device (different streams, different threads
+ * without ordering) race on it; calls ordered on one stream do not.
+ */
+#define VP_POISSON_NOALLOC_MAX_POINTS (512 * 512)
+VP4D_API vp_status vp_poisson_noalloc(int degree, int64_t n1, int64_t n2, double L1, double L2,
+                             const double* rho, double* E1, double* E2, double* W_el,
+                             void* stream);
+
+/*
  * vp_moments -- diagnostics of Sec. 4: mass = int f, L1 = int |f|,
  * L2 = (int f^2)^(1/2), kinetic energy = 1/2 int (v1^2 + v2^2) f, with the
  * nodal quadrature of the grid (degree as in vp_density).

@@ -225,6 +225,16 @@ def vp_poisson(degree, L1, L2, rho, E1, E2, W_el=None, workspace=None, stream=No
         _stream(stream)))
 
 
+def vp_poisson_noalloc(degree, L1, L2, rho, E1, E2, W_el=None, stream=None):
+    """vp_poisson without a workspace (C ABI ``vp_poisson_noalloc``): the
+    library's static device scratch, at most 512 x 512 points."""
+    n1, n2 = rho.shape
+    _check("vp_poisson_noalloc", lib().vp_poisson_noalloc(
+        int(degree), int(n1), int(n2), float(L1), float(L2), _f64(rho, "rho"),
+        _f64(E1, "E1", n1 * n2), _f64(E2, "E2", n1 * n2),
+        None if W_el is None else _f64(W_el, "W_el", 1), _stream(stream)))
+
+
 def vp_moments_workspace(dims):
     return int(lib().vp_moments_workspace(_lib.i64x4(dims)))
 

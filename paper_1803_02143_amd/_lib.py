@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "VP_OK", -1: "VP_ERR_ARG", -2: "VP_ERR_UNSUPPORTED",
 VP_F32 = 0
 VP_F64 = 1
 VP_TIMER_COUNT = 7
+VP_POISSON_NOALLOC_MAX_POINTS = 512 * 512
 TIMER_NAMES = ("sweep_x1", "sweep_x2", "sweep_v1", "sweep_v2", "field", "diag",
                "sweep_x2_rho")
 
@@ -43,6 +44,9 @@ SIGNATURES = {
                                   _vp, ctypes.c_size_t, _vp]),
     "vp_poisson_workspace": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int64,
                                                ctypes.c_int64]),
+    "vp_poisson_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                                          ctypes.c_double, ctypes.c_double, _dp, _dp, _dp,
+                                          _dp, _vp]),
     "vp_moments": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64x4, _vp, _dblx4,
                                   _dblx4, _dp, _vp, ctypes.c_size_t, _vp]),
     "vp_moments_workspace": (ctypes.c_size_t, [_i64x4]),

@@ -24,6 +24,7 @@
 //             along x2, E (and optionally the v-sweep shifts tau E/h_v),
 //             per-workgroup energy partial sums
 #include <cmath>
+#include <mutex>
 
 #include "field.hpp"
 
@@ -539,18 +540,49 @@ vp_status poisson_adjoint_impl(int degree, int64_t n1_, int64_t n2_, double L1, 
 
 }  // namespace vp
 
-extern "C" size_t vp_poisson_workspace(int degree, int64_t n1, int64_t n2) {
-    (void)degree;
-    if (n1 < 1 || n2 < 1) return 0;
-    return vp::poisson_ws_bytes(n1, n2);
+// ------------------------------------------------ allocation-free variant ---
+// The workspace of vp_poisson_noalloc: a device array of the library,
+// sized for the largest grid that entry point accepts.  Host code never
+// passes the array's name to a kernel (on the host it is a stand-in, not a
+// device address): its address on each device comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+namespace {
+constexpr size_t kNoAllocBytes =
+    sizeof(vp::Cplx) * 3 * static_cast<size_t>(VP_POISSON_NOALLOC_MAX_POINTS) +
+    sizeof(double) * 4096 + 256;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+// The address of `scratch` on the current device (looked up on the first
+// call on that device).
+vp_status scratch_on_current_device(void** out) {
+    using namespace vp;
+    int dev = -1;
+    VP_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return set_error(VP_ERR_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(VP_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                             hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return VP_OK;
 }
 
-extern "C" vp_status vp_poisson(int degree, int64_t n1, int64_t n2, double L1,
-                                double L2, const double* rho, double* E1,
-                                double* E2, double* W_el, void* workspace,
-                                size_t ws_bytes, void* stream) {
+// Host checks shared by vp_poisson and vp_poisson_noalloc.
+vp_status check_poisson_args(int degree, int64_t n1, int64_t n2, double L1, double L2,
+                             const double* rho, const double* E1, const double* E2) {
     using namespace vp;
-    clear_error();
     if (degree < -1 || degree > VP_MAX_DEGREE)
         return set_error(VP_ERR_UNSUPPORTED, "degree %d not in -1..%d", degree, VP_MAX_DEGREE);
     if (n1 < 1 || n2 < 1 || n1 > 4096 || n2 > 4096)
@@ -563,6 +595,24 @@ extern "C" vp_status vp_poisson(int degree, int64_t n1, int64_t n2, double L1,
     const size_t nb = sizeof(double) * static_cast<size_t>(n1 * n2);
     if (ranges_overlap(E1, E2, nb) || ranges_overlap(rho, E1, nb) || ranges_overlap(rho, E2, nb))
         return set_error(VP_ERR_ALIAS, "rho, E1 and E2 must not overlap");
+    return VP_OK;
+}
+}  // namespace
+
+extern "C" size_t vp_poisson_workspace(int degree, int64_t n1, int64_t n2) {
+    (void)degree;
+    if (n1 < 1 || n2 < 1) return 0;
+    return vp::poisson_ws_bytes(n1, n2);
+}
+
+extern "C" vp_status vp_poisson(int degree, int64_t n1, int64_t n2, double L1,
+                                double L2, const double* rho, double* E1,
+                                double* E2, double* W_el, void* workspace,
+                                size_t ws_bytes, void* stream) {
+    using namespace vp;
+    clear_error();
+    vp_status rc = check_poisson_args(degree, n1, n2, L1, L2, rho, E1, E2);
+    if (rc != VP_OK) return rc;
     if (!workspace || ws_bytes < poisson_ws_bytes(n1, n2))
         return set_error(VP_ERR_WORKSPACE, "workspace of %zu bytes needed",
                          poisson_ws_bytes(n1, n2));
@@ -593,4 +643,22 @@ extern "C" vp_status vp_poisson_adjoint(int degree, int64_t n1, int64_t n2, doub
                          poisson_ws_bytes(n1, n2));
     return poisson_adjoint_impl(degree, n1, n2, L1, L2, G1, G2, rho_bar, workspace, false,
                                 static_cast<hipStream_t>(stream));
+}
+
+extern "C" vp_status vp_poisson_noalloc(int degree, int64_t n1, int64_t n2, double L1,
+                                        double L2, const double* rho, double* E1,
+                                        double* E2, double* W_el, void* stream) {
+    using namespace vp;
+    clear_error();
+    vp_status rc = check_poisson_args(degree, n1, n2, L1, L2, rho, E1, E2);
+    if (rc != VP_OK) return rc;
+    if (n1 * n2 > VP_POISSON_NOALLOC_MAX_POINTS || poisson_ws_bytes(n1, n2) > kNoAllocBytes)
+        return set_error(VP_ERR_WORKSPACE,
+                         "grid %lld x %lld: the allocation-free Poisson solve holds at most "
+                         "%d points",
+                         (long long)n1, (long long)n2, VP_POISSON_NOALLOC_MAX_POINTS);
+    void* ws = nullptr;
+    if ((rc = scratch_on_current_device(&ws)) != VP_OK) return rc;
+    return poisson_impl(degree, n1, n2, L1, L2, rho, E1, E2, W_el, ws,
+                        static_cast<hipStream_t>(stream));
 }

@@ -138,3 +138,22 @@ def test_binding_fails_loudly_without_library(tmp_path):
             L.load(str(tmp_path / "missing.so"))
     finally:
         L._LIB = saved
+
+
+def test_noalloc_poisson_rejects_before_touching_the_device():
+    # the allocation-free Poisson solve validates like vp_poisson and refuses
+    # grids beyond its static scratch before any HIP call
+    L, lib = _lib()
+    a, b, c = _fake(), _fake(), _fake()
+    pa, pb, pc = (ctypes.cast(x, ctypes.c_void_p) for x in (a, b, c))
+    assert L.VP_POISSON_NOALLOC_MAX_POINTS == 512 * 512
+    # (addresses far apart that are never dereferenced: the check fails first)
+    far = [ctypes.c_void_p(k << 32) for k in (1, 2, 3)]
+    assert lib.vp_poisson_noalloc(2, 516, 516, 1.0, 1.0, *far, None, None) == \
+        L.VP_ERR_WORKSPACE
+    assert "at most" in lib.vp_last_error().decode()
+    assert lib.vp_poisson_noalloc(2, 7, 6, 1.0, 1.0, pa, pb, pc, None, None) == L.VP_ERR_ARG
+    assert lib.vp_poisson_noalloc(2, 6, 6, 1.0, 1.0, pa, pb, pb, None, None) == L.VP_ERR_ALIAS
+    assert lib.vp_poisson_noalloc(9, 6, 6, 1.0, 1.0, pa, pb, pc, None, None) == \
+        L.VP_ERR_UNSUPPORTED
+
