@@ -7,6 +7,7 @@
 // with the nodal quadrature (Gauss-Legendre weights times the cell width for
 // SLDG, the spacing for the spline grid) and reduces in FP64 by cross-lane
 // shuffles.  No atomics, so results are deterministic.
+#include <algorithm>
 #include <cmath>
 
 #include "vp4d_internal.hpp"
@@ -209,16 +210,15 @@ rho_from_parts(const double* __restrict__ part, int64_t groups, int64_t n2,
     const int64_t j = static_cast<int64_t>(blockIdx.x) * 64 + lane;
     const int64_t jc = j < n2 ? j : n2 - 1;
     const double* __restrict__ p = part + a * groups * n2 + jc;
-    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    // eight independent accumulators: eight loads of each wavefront in flight
+    double t[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int64_t g = wave;
-    for (; g + 12 < groups; g += 16) {
-        t0 += p[g * n2];
-        t1 += p[(g + 4) * n2];
-        t2 += p[(g + 8) * n2];
-        t3 += p[(g + 12) * n2];
+    for (; g + 28 < groups; g += 32) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] += p[(g + 4 * u) * n2];
     }
-    for (; g < groups; g += 4) t0 += p[g * n2];
-    red[wave][lane] = (t0 + t1) + (t2 + t3);
+    for (; g < groups; g += 4) t[0] += p[g * n2];
+    red[wave][lane] = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
     __syncthreads();
     if (wave == 0 && j < n2)
         rho[a * n2 + j] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
@@ -250,6 +250,36 @@ moments_from_parts(const double* __restrict__ part, int64_t nparts, double* __re
         if (threadIdx.x == 2) t = sqrt(t);
         if (threadIdx.x == 3) t *= 0.5;
         out4[threadIdx.x] = t;
+    }
+}
+
+// First stage of a long moments_from_parts: block b adds the parts of its
+// contiguous chunk [b per, (b+1) per) (thread t: parts t, t + 256, ... of
+// the chunk, then a fixed-order block reduction) into chunk[4 b + k].
+constexpr int kChunkBlock = 256;
+constexpr int kMaxChunks = 512;
+__global__ void __launch_bounds__(kChunkBlock)
+moments_chunks(const double* __restrict__ part, int64_t nparts, int64_t per,
+               double* __restrict__ chunk) {
+    __shared__ double red[4][kChunkBlock / 64];
+    const int64_t q0 = static_cast<int64_t>(blockIdx.x) * per;
+    const int64_t q1 = min(nparts, q0 + per);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += kChunkBlock)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] += part[4 * q + k];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double v = wave_sum64(acc[k]);
+        if (lane == 0) red[k][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+        for (int w = 0; w < kChunkBlock / 64; ++w) t += red[threadIdx.x][w];
+        chunk[4 * static_cast<int64_t>(blockIdx.x) + threadIdx.x] = t;
     }
 }
 
@@ -385,15 +415,30 @@ vp_status launch_reduce(bool diag, const int64_t dims[4], const void* f,
 
 }  // namespace
 
-vp_status moments_from_parts_impl(const double* mom_part, int64_t nparts, double* out4,
-                                  hipStream_t st) {
+vp_status moments_from_parts_impl(const double* mom_part, int64_t nparts, double* chunk,
+                                  double* out4, hipStream_t st) {
+    // one block reads at most a few hundred kB quickly; beyond that the parts
+    // are first added in up to kMaxChunks contiguous chunks by as many blocks
+    if (nparts > 4 * kFinalBlock && chunk) {
+        const int64_t nb = std::min<int64_t>(kMaxChunks, (nparts + 4 * kFinalBlock - 1) / (4 * kFinalBlock));
+        const int64_t per = (nparts + nb - 1) / nb;
+        const int64_t used = (nparts + per - 1) / per;
+        moments_chunks<<<static_cast<unsigned>(used), kChunkBlock, 0, st>>>(mom_part, nparts,
+                                                                           per, chunk);
+        vp_status rc = check_launch("moments_chunks");
+        if (rc != VP_OK) return rc;
+        moments_from_parts<<<1, kFinalBlock, 0, st>>>(chunk, used, out4);
+        return check_launch("moments_from_parts");
+    }
     moments_from_parts<<<1, kFinalBlock, 0, st>>>(mom_part, nparts, out4);
     return check_launch("moments_from_parts");
 }
 
-int64_t rho_fuse_workgroups(int method, vp_dtype dt, const int64_t dims[4]) {
+size_t moments_chunk_doubles() { return 4 * static_cast<size_t>(kMaxChunks); }
+
+int64_t rho_fuse_workgroups(int method, int degree, vp_dtype dt, const int64_t dims[4]) {
     const int64_t nvel = dims[2] * dims[3];
-    if (method == 0) return nvel % 256 == 0 ? dims[0] * nvel / 256 : 0;
+    if (method == 0) return sldg_rho_workgroups(dt, degree, dims);
     const int gsz = spline_rho_group(dt, dims);
     return gsz > 0 ? dims[0] * nvel / gsz : 0;
 }

@@ -39,6 +39,12 @@ struct RhoFuse {
 // path for this grid); the SLDG one uses groups of 256 columns when N3 N4 is
 // a multiple of 256.
 int spline_rho_group(vp_dtype dt, const int64_t dims[4]);
+// Velocity columns per thread of the fused SLDG x2 sweep (J columns that
+// share the x2 shift: one v2, J consecutive v1 nodes), so a workgroup holds
+// 256 J columns; 0 when N3 N4 is no multiple of 256 (no fused path).
+int sldg_rho_stack(vp_dtype dt, int degree, const int64_t dims[4]);
+// Workgroups of the fused SLDG x2 sweep (one moment partial each).
+int64_t sldg_rho_workgroups(vp_dtype dt, int degree, const int64_t dims[4]);
 vp_status sldg_advect_rho_impl(int degree, vp_dtype dt, const int64_t dims[4],
                                const void* f_in, void* f_out, const double* shift,
                                const int64_t shift_stride[4], const RhoFuse& rf,
@@ -49,11 +55,13 @@ vp_status spline_advect_rho_impl(vp_dtype dt, const int64_t dims[4], const void*
                                  hipStream_t st);
 vp_status rho_from_parts_impl(const double* part, int64_t n1, int64_t groups, int64_t n2,
                               double* rho, hipStream_t st);
-// out4 = (mass, L1, L2, kinetic energy) from nparts workgroup sums (4 each)
-vp_status moments_from_parts_impl(const double* mom_part, int64_t nparts, double* out4,
-                                  hipStream_t st);
+// out4 = (mass, L1, L2, kinetic energy) from nparts workgroup sums (4 each);
+// `chunk` (moments_chunk_doubles() doubles) holds the first stage of long sums
+vp_status moments_from_parts_impl(const double* mom_part, int64_t nparts, double* chunk,
+                                  double* out4, hipStream_t st);
+size_t moments_chunk_doubles();
 // workgroups of the fused x2 sweep (the number of mom_part entries / 4)
-int64_t rho_fuse_workgroups(int method, vp_dtype dt, const int64_t dims[4]);
+int64_t rho_fuse_workgroups(int method, int degree, vp_dtype dt, const int64_t dims[4]);
 
 // Sweep (adjoint = false) or its transpose for fixed shifts (adjoint = true).
 vp_status sldg_advect_impl(int axis, int degree, vp_dtype dt,

@@ -37,6 +37,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kU = 8;  // loads issued back to back per thread
+constexpr int kSegCells = 8;  // output cells per thread of the segmented column sweep
 
 template <int M>
 __device__ __forceinline__ void lagrange_all(const NodeBasis& b, double t,
@@ -267,15 +268,81 @@ sldg_col(const T* __restrict__ fin, T* __restrict__ fout,
     }
 }
 
+// Strided lines by row segments.  A thread forms the C output cells
+// [q C, q C + C) of one line (fewer at the end of the line): output cell i
+// reads input cells i + d and i + d + 1 (d = -s - 1, or s for the transpose),
+// so the segment loads its C + 1 input cells at once, one of them the
+// previous segment's last (a re-read that the caches serve).  Blocks run in
+// memory order: when a workgroup's 256 lines share the outer index (inner a
+// multiple of 256) block b is (outer o, segment q, column block kb) with kb
+// fastest, so that the workgroups in flight cover a narrow band of rows
+// instead of every row of their columns at once; otherwise b is (line
+// block, segment) with the segment fastest.  Short-lived workgroups whose
+// accesses advance through memory in block order stream like a plain copy,
+// where one thread per whole line (sldg_col) keeps every row of the array
+// in flight at the same time.
+template <int M, typename T, bool ADJ, int C, bool BAND>
+__global__ void __launch_bounds__(kBlock)
+sldg_seg(const T* __restrict__ fin, T* __restrict__ fout,
+         const double* __restrict__ shift, ShiftMap sm, int64_t outer, int nc,
+         int64_t inner, int nseg, NodeBasis basis) {
+    int64_t o, k;
+    int q;
+    if (BAND) {
+        const int64_t nkb = inner / kBlock;
+        const int64_t b = blockIdx.x;
+        const int64_t kb = b % nkb;
+        const int64_t rest = b / nkb;
+        q = static_cast<int>(rest % nseg);
+        o = rest / nseg;
+        k = kb * kBlock + threadIdx.x;
+    } else {
+        q = static_cast<int>(blockIdx.x % nseg);
+        const int64_t line = static_cast<int64_t>(blockIdx.x / nseg) * kBlock + threadIdx.x;
+        if (line >= outer * inner) return;
+        o = line / inner;
+        k = line - o * inner;
+    }
+    int s;
+    T A[M][M], B[M][M];
+    sldg_operator<M, T>(basis, shift[shift_offset(sm, o, k)], nc, s, A, B);
+    if (ADJ) transpose_pair<M, T>(A, B);
+
+    const int64_t cs = static_cast<int64_t>(M) * inner;  // cell stride
+    const T* __restrict__ src = fin + o * nc * cs + k;
+    T* __restrict__ dst = fout + o * nc * cs + k;
+    const int i0 = q * C;
+    // first input cell i0 + d, reduced into [0, nc)
+    int c = ADJ ? i0 + s : i0 - s - 1;
+    c += c < 0 ? nc : 0;
+    c -= c >= nc ? nc : 0;
+    T u[C + 1][M];
+#pragma unroll
+    for (int j = 0; j <= C; ++j) {
+#pragma unroll
+        for (int l = 0; l < M; ++l) u[j][l] = src[c * cs + l * inner];
+        c = c + 1 == nc ? 0 : c + 1;
+    }
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+        if (i0 + j < nc) sldg_cell<M, T>(A, B, u[j], u[j + 1], dst + (i0 + j) * cs, inner);
+}
+
 // The x2 sweep with its output density formed on the way (forward only).
-// Output cells are produced in order, every lane of a wavefront on the same
-// cell: output i is fed by input cells (l0 + i, l0 + i + 1) mod n_c with
-// l0 = n_c - 1 - s, which lanes load from their own (shift-dependent) rows.
-// The weighted values W3 W4 f_out of CU cells are reduce-scattered across
-// the wavefront; the four wavefronts' sums meet in LDS, and each workgroup
-// writes the partial density of its 256 velocity columns (inner must be a
-// multiple of the workgroup size).  Every input cell is loaded once.
-template <int M, typename T, bool MOM>
+// The x2 shift depends on v2 only, so a thread takes J velocity columns
+// that share it: the same v2 and J consecutive v1 nodes (columns k0 + j N4),
+// with one operator for all of them.  Output cells are produced in order,
+// every lane of a wavefront on the same cell: output i is fed by input
+// cells (l0 + i, l0 + i + 1) mod n_c with l0 = n_c - 1 - s, which lanes load
+// from their own (shift-dependent) rows.  A lane first adds W3 W4 f_out
+// over its J columns, then the wavefront reduce-scatters those per-cell
+// values (one exchange per J columns) while the next cells' loads are in
+// flight; the four wavefronts' sums meet in LDS, and each workgroup writes
+// the partial density of its 256 J velocity columns (N3 / J N4 must be a
+// multiple of the workgroup size).  Every input cell is loaded once.  (A
+// row-segmented form, as for the plain sweeps, ran slower here: its
+// reductions come after all of its loads, with nothing left to overlap.)
+template <int M, typename T, int J, bool MOM>
 __global__ void __launch_bounds__(kBlock)
 sldg_col_rho(const T* __restrict__ fin, T* __restrict__ fout,
              const double* __restrict__ shift, ShiftMap sm, int nc, int64_t inner,
@@ -283,142 +350,175 @@ sldg_col_rho(const T* __restrict__ fin, T* __restrict__ fout,
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = nc * M;
     double* rp = reinterpret_cast<double*>(smem);   // [kBlock / 64][N]
+    const int64_t tpo = inner / J;                  // threads per x1 index
     const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    const int64_t o = gid / inner;
-    const int64_t k = gid - o * inner;
+    const int64_t o = gid / tpo;
+    const int t = static_cast<int>(gid - o * tpo);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int v1 = static_cast<int>(k / rf.n4);
-    const int v2 = static_cast<int>(k - static_cast<int64_t>(v1) * rf.n4);
-    const double wk = rf.g3.w[v1 % rf.g3.m] * rf.g3.h * (rf.g4.w[v2 % rf.g4.m] * rf.g4.h);
+    const int v1b = t / rf.n4;                      // J v1 nodes v1b J .. v1b J + J - 1
+    const int v2 = t - v1b * rf.n4;
+    const int64_t k0 = static_cast<int64_t>(v1b) * J * rf.n4 + v2;
+    const int64_t js = rf.n4;                       // column step between them
+    const double w4v = rf.g4.w[v2 % rf.g4.m] * rf.g4.h;
+    double wk[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) wk[j] = rf.g3.w[(v1b * J + j) % rf.g3.m] * rf.g3.h * w4v;
 
     int s;
     T A[M][M], B[M][M];
-    sldg_operator<M, T>(basis, shift[shift_offset(sm, o, k)], nc, s, A, B);
+    sldg_operator<M, T>(basis, shift[shift_offset(sm, o, k0)], nc, s, A, B);
     const int64_t cs = static_cast<int64_t>(M) * inner;
-    const T* __restrict__ src = fin + o * nc * cs + k;
-    T* __restrict__ dst = fout + o * nc * cs + k;
+    const T* __restrict__ src = fin + o * nc * cs + k0;
+    T* __restrict__ dst = fout + o * nc * cs + k0;
 
     const int l0 = nc - 1 - s;
-    T first[M], prev[M];
+    T first[J][M], prev[J][M];
 #pragma unroll
-    for (int l = 0; l < M; ++l) {
-        first[l] = src[l0 * cs + l * inner];
-        prev[l] = first[l];
-    }
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            first[j][l] = src[l0 * cs + l * inner + j * js];
+            prev[j][l] = first[j][l];
+        }
     int rc = l0 + 1 == nc ? 0 : l0 + 1;   // next input cell to load
-    // moments: sums over this column of W2 f, W2 |f|, W2 f^2 (x2 weights)
-    double s_m = 0.0, s_a = 0.0, s_q = 0.0;
+    // moments: sums over the thread's columns of W2 W3 f, W2 W3 |f|,
+    // W2 W3 f^2 and W2 W3 |v|^2 f (W4 and W1 are applied at the end)
+    double s_m = 0.0, s_a = 0.0, s_q = 0.0, s_k = 0.0;
     double w2[M];
 #pragma unroll
-    for (int j = 0; j < M; ++j) w2[j] = MOM ? rf.g2.w[j] * rf.g2.h : 0.0;
-    constexpr int CU = M <= 3 ? 4 : 2;          // cells whose loads are in flight together
-    constexpr int V = 2 * M <= 4 ? 4 : (2 * M <= 8 ? 8 : 16);   // two cells per reduction
+    for (int l = 0; l < M; ++l) w2[l] = MOM ? rf.g2.w[l] * rf.g2.h : 0.0;
+    double w3[J], vv[J];
+    if (MOM) {
+        const double a2 = rf.g4.lo + (static_cast<double>(v2 / rf.g4.m) + rf.g4.xi[v2 % rf.g4.m]) * rf.g4.h;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int v1 = v1b * J + j;
+            const double a1 = rf.g3.lo + (static_cast<double>(v1 / rf.g3.m) + rf.g3.xi[v1 % rf.g3.m]) * rf.g3.h;
+            w3[j] = rf.g3.w[v1 % rf.g3.m] * rf.g3.h;
+            vv[j] = a1 * a1 + a2 * a2;
+        }
+    }
+    // cells whose loads are in flight together (about 12 loads, an even
+    // number of cells when more than one), reduced two at a time
+    constexpr int CU0 = 12 / (J * M);
+    constexpr int CU = CU0 >= 2 ? (CU0 & ~1) : (J * M >= 12 ? 1 : 2);
+    constexpr int P = CU >= 2 ? 2 : 1;
+    static_assert(CU % P == 0, "whole reduction groups per batch");
+    constexpr int V = P * M <= 4 ? 4 : (P * M <= 8 ? 8 : 16);
     int i = 0;
     for (; i + CU <= nc - 1; i += CU) {
-        T cur[CU][M];
+        T cur[CU][J][M];
 #pragma unroll
         for (int u = 0; u < CU; ++u) {
             int c = rc + u;
             c -= c >= nc ? nc : 0;
 #pragma unroll
-            for (int l = 0; l < M; ++l) cur[u][l] = src[c * cs + l * inner];
+            for (int j = 0; j < J; ++j)
+#pragma unroll
+                for (int l = 0; l < M; ++l) cur[u][j][l] = src[c * cs + l * inner + j * js];
         }
 #pragma unroll
-        for (int h = 0; h < CU; h += 2) {
+        for (int h = 0; h < CU; h += P) {
             double vals[V];
 #pragma unroll
-            for (int t = 0; t < V; ++t) vals[t] = 0.0;
+            for (int q = 0; q < V; ++q) vals[q] = 0.0;
 #pragma unroll
-            for (int u = h; u < h + 2; ++u) {
+            for (int u = h; u < h + P; ++u) {
 #pragma unroll
-                for (int j = 0; j < M; ++j) {
-                    T acc = T(0);
+                for (int j = 0; j < J; ++j) {
 #pragma unroll
-                    for (int l = 0; l < M; ++l) acc = fma(A[j][l], prev[l], acc);
+                    for (int m = 0; m < M; ++m) {
+                        T acc = T(0);
 #pragma unroll
-                    for (int l = 0; l < M; ++l) acc = fma(B[j][l], cur[u][l], acc);
-                    put_out(&dst[(i + u) * cs + j * inner], acc);
-                    const double ov = static_cast<double>(acc);
-                    vals[(u - h) * M + j] = wk * ov;
-                    if (MOM) {
-                        s_m = fma(w2[j], ov, s_m);
-                        s_a = fma(w2[j], fabs(ov), s_a);
-                        s_q = fma(w2[j] * ov, ov, s_q);
+                        for (int l = 0; l < M; ++l) acc = fma(A[m][l], prev[j][l], acc);
+#pragma unroll
+                        for (int l = 0; l < M; ++l) acc = fma(B[m][l], cur[u][j][l], acc);
+                        put_out(&dst[(i + u) * cs + m * inner + j * js], acc);
+                        const double ov = static_cast<double>(acc);
+                        vals[(u - h) * M + m] = fma(wk[j], ov, vals[(u - h) * M + m]);
+                        if (MOM) {
+                            const double wv = w2[m] * w3[j];
+                            s_m = fma(wv, ov, s_m);
+                            s_a = fma(wv, fabs(ov), s_a);
+                            s_q = fma(wv * ov, ov, s_q);
+                            s_k = fma(wv * vv[j], ov, s_k);
+                        }
                     }
-                }
 #pragma unroll
-                for (int l = 0; l < M; ++l) prev[l] = cur[u][l];
+                    for (int l = 0; l < M; ++l) prev[j][l] = cur[u][j][l];
+                }
             }
             const double r = group_reduce_scatter<V, 64>(vals, lane);
-            if (lane < 2 * M) rp[wave * N + (i + h) * M + lane] = r;
+            if (lane < P * M) rp[wave * N + (i + h) * M + lane] = r;
         }
         rc += CU;
         rc -= rc >= nc ? nc : 0;
     }
     constexpr int VT = M <= 4 ? 4 : 8;
     for (; i < nc; ++i) {
-        T cur[M];
-        if (i < nc - 1) {
+        T cur[J][M];
 #pragma unroll
-            for (int l = 0; l < M; ++l) cur[l] = src[rc * cs + l * inner];
-        } else {
+        for (int j = 0; j < J; ++j)
 #pragma unroll
-            for (int l = 0; l < M; ++l) cur[l] = first[l];
-        }
+            for (int l = 0; l < M; ++l)
+                cur[j][l] = i < nc - 1 ? src[rc * cs + l * inner + j * js] : first[j][l];
         double vals[VT];
 #pragma unroll
-        for (int t = 0; t < VT; ++t) vals[t] = 0.0;
+        for (int q = 0; q < VT; ++q) vals[q] = 0.0;
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-            T acc = T(0);
+        for (int j = 0; j < J; ++j) {
 #pragma unroll
-            for (int l = 0; l < M; ++l) acc = fma(A[j][l], prev[l], acc);
+            for (int m = 0; m < M; ++m) {
+                T acc = T(0);
 #pragma unroll
-            for (int l = 0; l < M; ++l) acc = fma(B[j][l], cur[l], acc);
-            put_out(&dst[i * cs + j * inner], acc);
-            const double ov = static_cast<double>(acc);
-            vals[j] = wk * ov;
-            if (MOM) {
-                s_m = fma(w2[j], ov, s_m);
-                s_a = fma(w2[j], fabs(ov), s_a);
-                s_q = fma(w2[j] * ov, ov, s_q);
+                for (int l = 0; l < M; ++l) acc = fma(A[m][l], prev[j][l], acc);
+#pragma unroll
+                for (int l = 0; l < M; ++l) acc = fma(B[m][l], cur[j][l], acc);
+                put_out(&dst[i * cs + m * inner + j * js], acc);
+                const double ov = static_cast<double>(acc);
+                vals[m] = fma(wk[j], ov, vals[m]);
+                if (MOM) {
+                    const double wv = w2[m] * w3[j];
+                    s_m = fma(wv, ov, s_m);
+                    s_a = fma(wv, fabs(ov), s_a);
+                    s_q = fma(wv * ov, ov, s_q);
+                    s_k = fma(wv * vv[j], ov, s_k);
+                }
             }
+#pragma unroll
+            for (int l = 0; l < M; ++l) prev[j][l] = cur[j][l];
         }
         const double r = group_reduce_scatter<VT, 64>(vals, lane);
         if (lane < M) rp[wave * N + i * M + lane] = r;
-#pragma unroll
-        for (int l = 0; l < M; ++l) prev[l] = cur[l];
         rc = rc + 1 == nc ? 0 : rc + 1;
     }
     if (MOM) {
-        // W = W1 W2 W3 W4; |v|^2 is constant on a velocity column
+        // W = W1 W2 W3 W4 (W2 W3 already in the sums)
         const double w1 = rf.g1.w[o % rf.g1.m] * rf.g1.h;
-        const double a1 = rf.g3.lo + (static_cast<double>(v1 / rf.g3.m) + rf.g3.xi[v1 % rf.g3.m]) * rf.g3.h;
-        const double a2 = rf.g4.lo + (static_cast<double>(v2 / rf.g4.m) + rf.g4.xi[v2 % rf.g4.m]) * rf.g4.h;
-        const double f0 = w1 * wk;
-        double q[4] = {f0 * s_m, f0 * s_a, f0 * s_q, f0 * (a1 * a1 + a2 * a2) * s_m};
+        const double f0 = w1 * w4v;
+        double q[4] = {f0 * s_m, f0 * s_a, f0 * s_q, f0 * s_k};
         double* red = rp + (kBlock / 64) * N;   // [4][kBlock / 64]
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t4 = 0; t4 < 4; ++t4) {
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) q[t] += __shfl_xor(q[t], off, 64);
-            if (lane == 0) red[t * (kBlock / 64) + wave] = q[t];
+            for (int off = 32; off > 0; off >>= 1) q[t4] += __shfl_xor(q[t4], off, 64);
+            if (lane == 0) red[t4 * (kBlock / 64) + wave] = q[t4];
         }
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < N; j += kBlock) {
-        double t = 0.0;
+    for (int jj = threadIdx.x; jj < N; jj += kBlock) {
+        double acc = 0.0;
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) t += rp[w * N + j];
-        rf.part[static_cast<int64_t>(blockIdx.x) * N + j] = t;
+        for (int w = 0; w < kBlock / 64; ++w) acc += rp[w * N + jj];
+        rf.part[static_cast<int64_t>(blockIdx.x) * N + jj] = acc;
     }
     if (MOM && threadIdx.x < 4) {
         const double* red = rp + (kBlock / 64) * N;
-        double t = 0.0;
+        double acc = 0.0;
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) t += red[threadIdx.x * (kBlock / 64) + w];
-        rf.mom_part[static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x] = t;
+        for (int w = 0; w < kBlock / 64; ++w) acc += red[threadIdx.x * (kBlock / 64) + w];
+        rf.mom_part[static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x] = acc;
     }
 }
 
@@ -540,6 +640,19 @@ vp_status launch_sldg(int axis, const int64_t dims[4], const void* fin,
     const T* in = static_cast<const T*>(fin);
     T* out = static_cast<T*>(fout);
     if (axis < 3) {
+        constexpr int C = kSegCells;
+        const int nseg = (nc + C - 1) / C;
+        const bool band = inner % kBlock == 0;
+        const int64_t nblk = band ? outer * nseg * (inner / kBlock)
+                                  : static_cast<int64_t>(blocks_for(outer * inner, kBlock)) * nseg;
+        if (nblk < (int64_t(1) << 31)) {
+            const unsigned g = static_cast<unsigned>(nblk);
+            if (band)
+                sldg_seg<M, T, ADJ, C, true><<<g, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, nseg, b);
+            else
+                sldg_seg<M, T, ADJ, C, false><<<g, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, nseg, b);
+            return check_launch("sldg_seg");
+        }
         const unsigned grid = blocks_for(outer * inner, kBlock);
         switch (axis) {
             case 0:
@@ -582,25 +695,42 @@ vp_status dispatch_degree(int degree, int axis, const int64_t dims[4],
     }
 }
 
-template <int M, typename T>
-vp_status launch_sldg_rho(const int64_t dims[4], const void* fin, void* fout,
-                          const double* shift, const ShiftMap& sm, const RhoFuse& rf,
-                          hipStream_t st) {
+template <int M, typename T, int J>
+vp_status launch_sldg_rho_j(const int64_t dims[4], const void* fin, void* fout,
+                            const double* shift, const ShiftMap& sm, const RhoFuse& rf,
+                            hipStream_t st) {
     const NodeBasis& b = node_basis(M - 1);
     const int64_t outer = dims[0];
     const int64_t inner = dims[2] * dims[3];
     const int nc = static_cast<int>(dims[1] / M);
     const size_t lds = sizeof(double) * (kBlock / 64) * (static_cast<size_t>(dims[1]) + 4);
-    if (inner % kBlock || lds > 48 * 1024)
+    if (dims[2] % J || (inner / J) % kBlock || lds > 48 * 1024)
         return set_error(VP_ERR_UNSUPPORTED, "fused x2 sweep needs whole workgroups of columns");
-    const unsigned grid = blocks_for(outer * inner, kBlock);
+    const unsigned grid = blocks_for(outer * inner / J, kBlock);
     if (rf.mom_part)
-        sldg_col_rho<M, T, true><<<grid, kBlock, lds, st>>>(
+        sldg_col_rho<M, T, J, true><<<grid, kBlock, lds, st>>>(
             static_cast<const T*>(fin), static_cast<T*>(fout), shift, sm, nc, inner, b, rf);
     else
-        sldg_col_rho<M, T, false><<<grid, kBlock, lds, st>>>(
+        sldg_col_rho<M, T, J, false><<<grid, kBlock, lds, st>>>(
             static_cast<const T*>(fin), static_cast<T*>(fout), shift, sm, nc, inner, b, rf);
     return check_launch("sldg_col_rho");
+}
+
+template <int M, typename T>
+vp_status launch_sldg_rho(const int64_t dims[4], const void* fin, void* fout,
+                          const double* shift, const ShiftMap& sm, const RhoFuse& rf,
+                          hipStream_t st) {
+    const int J = sldg_rho_stack(sizeof(T) == 8 ? VP_F64 : VP_F32, M - 1, dims);
+    if (J == 4) {
+        if constexpr (M <= 3 && sizeof(T) == 4)
+            return launch_sldg_rho_j<M, T, 4>(dims, fin, fout, shift, sm, rf, st);
+    }
+    if (J == 2) {
+        if constexpr (M <= 4)
+            return launch_sldg_rho_j<M, T, 2>(dims, fin, fout, shift, sm, rf, st);
+    }
+    if (J == 1) return launch_sldg_rho_j<M, T, 1>(dims, fin, fout, shift, sm, rf, st);
+    return set_error(VP_ERR_UNSUPPORTED, "fused x2 sweep needs whole workgroups of columns");
 }
 
 template <typename T>
@@ -817,10 +947,28 @@ vp_status sldg_advect_impl(int axis, int degree, vp_dtype dt,
                : dispatch_degree<float, false>(degree, axis, dims, f_in, f_out, shift, sm, st);
 }
 
+int sldg_rho_stack(vp_dtype dt, int degree, const int64_t dims[4]) {
+    const int64_t inner = dims[2] * dims[3];
+    // FP32, degree <= 2: four columns a thread (the FP32 sweep has half the
+    // memory time to hide the density exchanges behind); otherwise, or where
+    // the grid does not divide, one
+    int J = degree <= 2 && dt == VP_F32 ? 4 : 1;
+    while (J > 1 && (dims[2] % J || (inner / J) % kBlock)) J /= 2;
+    if (inner % kBlock && J == 1) return 0;
+    return J;
+}
+
+int64_t sldg_rho_workgroups(vp_dtype dt, int degree, const int64_t dims[4]) {
+    const int J = sldg_rho_stack(dt, degree, dims);
+    return J > 0 ? dims[0] * dims[2] * dims[3] / (static_cast<int64_t>(kBlock) * J) : 0;
+}
+
 vp_status sldg_advect_rho_impl(int degree, vp_dtype dt, const int64_t dims[4],
                                const void* f_in, void* f_out, const double* shift,
                                const int64_t shift_stride[4], const RhoFuse& rf,
                                hipStream_t st) {
+    if (sldg_rho_stack(dt, degree, dims) > 1 && shift_stride[2] != 0)
+        return set_error(VP_ERR_UNSUPPORTED, "fused x2 sweep: the shift must not depend on v1");
     const ShiftMap sm = make_shift_map(1, dims, shift_stride);
     if (dt == VP_F64)
         return dispatch_rho<double>(degree, dims, f_in, f_out, shift, sm, rf, st);

@@ -29,6 +29,7 @@ struct vp_state {
     double* rho_part;           // partial densities of the fused x2 sweep
     int64_t rho_groups;         // column groups per x1 (0: no fused x2 sweep)
     double* mom_part;           // its per-workgroup moment sums (4 each)
+    double* mom_chunk;          // first-stage sums of long mom_part arrays
     int64_t mom_parts;          // workgroups of the fused x2 sweep
     double* partial;  // 4 * n1 * n2
     double *gs1, *gs2, *rho_bar;  // adjoint: shift gradients and transposed density
@@ -125,7 +126,7 @@ vp_status sweep_x2_rho(vp_state* st, const void* in, void* out, const double* sh
 vp_status diagnostics_fused(vp_state* st, double* W, double* mom, hipStream_t s) {
     mark(st, VP_TIMER_DIAG, s);
     vp_status rc = VP_OK;
-    if (mom) rc = moments_from_parts_impl(st->mom_part, st->mom_parts, mom, s);
+    if (mom) rc = moments_from_parts_impl(st->mom_part, st->mom_parts, st->mom_chunk, mom, s);
     if (rc == VP_OK && W)
         rc = rho_from_parts_impl(st->rho_part, st->dims[0], st->rho_groups, st->dims[1],
                                  st->rho, s);
@@ -227,22 +228,23 @@ extern "C" vp_status vp_create(vp_state** out, int method, int degree, vp_dtype 
     const int64_t nx = dims[0] * dims[1];
     const size_t pws = vp_poisson_workspace(deg, dims[0], dims[1]);
     // the x2 sweep forms the density of its output in groups of velocity
-    // columns: 256 per workgroup for SLDG, 64 per tile for the spline
+    // columns: 256 J per workgroup for SLDG (J columns a thread), 64 or 32
+    // per tile for the spline
     const int64_t nvel = dims[2] * dims[3];
     int64_t groups = 0;
-    // (SLDG: whole workgroups of 256 columns, and the four wavefronts' N2
+    // (SLDG: whole workgroups of 256 J columns, and the four wavefronts' N2
     // partial sums in 48 KiB of LDS)
-    if (method == 0 && nvel % 256 == 0 && 4 * (dims[1] + 4) * 8 <= 48 * 1024)
-        groups = nvel / 256;
+    if (method == 0 && sldg_rho_stack(dt, deg, dims) > 0 && 4 * (dims[1] + 4) * 8 <= 48 * 1024)
+        groups = nvel / (256 * sldg_rho_stack(dt, deg, dims));
     if (method == 1 && spline_rho_group(dt, dims) > 0) groups = nvel / spline_rho_group(dt, dims);
     // (not worth more than a sixteenth of a state in partial sums)
     const size_t fbytes = static_cast<size_t>(total) * dtype_size(dt);
     if (static_cast<size_t>(dims[0] * groups * dims[1]) * sizeof(double) > fbytes / 16) groups = 0;
     const size_t npart = static_cast<size_t>(dims[0] * groups * dims[1]);
-    const int64_t nwg = groups > 0 ? rho_fuse_workgroups(method, dt, dims) : 0;
+    const int64_t nwg = groups > 0 ? rho_fuse_workgroups(method, deg, dt, dims) : 0;
     const size_t ndbl = static_cast<size_t>(nx) * (5 + 4 + 3) +
                         3 * static_cast<size_t>(dims[2] + dims[3]) + pws / sizeof(double) + 64 +
-                        npart + 4 * static_cast<size_t>(nwg) + 32;
+                        npart + 4 * static_cast<size_t>(nwg) + moments_chunk_doubles() + 32;
     void* mem = nullptr;
     hipError_t e = hipMalloc(&mem, ndbl * sizeof(double));
     if (e != hipSuccess) {
@@ -273,6 +275,8 @@ extern "C" vp_status vp_create(vp_state** out, int method, int degree, vp_dtype 
     st->mom_parts = nwg;
     st->mom_part = p;
     p += 4 * nwg;
+    st->mom_chunk = p;
+    p += moments_chunk_doubles();
     p = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(p) + 255) & ~uintptr_t(255));
     st->pws = p;
     // velocity node coordinates, used for the x-sweep shifts

@@ -31,6 +31,10 @@ SLDG_CASES = [
     ((2, 2, 2, 3), 5),
     ((1, 3, 2, 4), 2),        # a single cell along x1
     ((11, 3, 2, 37), 2),      # strided lines longer than a wavefront, long rows
+    # whole workgroups of columns along x1 and x2 (row-segment blocks in
+    # memory order), lines that end in a partial segment of cells
+    ((3, 5, 4, 16), 3),
+    ((11, 9, 4, 16), 1),
 ]
 
 

@@ -176,11 +176,21 @@ def test_full_size_step_parity(method, dt):
                     tdt, w.dofs, w.lo, w.length)
     fd = to_dev(f0, dt)
     tmp = torch.empty_like(fd)
+    W = torch.empty(2, dtype=torch.float64, device="cuda")
+    mom = torch.empty(8, dtype=torch.float64, device="cuda")
     announce(f"full size step {method} {dt}: device step")
-    st.step(fd, tmp, 1, w.dt)
+    st.step(fd, tmp, 1, w.dt, W, mom)
     got = to_host(fd)
     del fd, tmp
     st.close()
+    # W and the moments of f^1 from the fused x2 sweep's partial sums (the
+    # spline's 13824 workgroup sums take the two-stage moment reduction)
+    g = _grid(w, method)
+    W_ref = strang.electric_field(ref, g)[2]
+    m_ref = np.array(field.moments(ref, g.degree, g.lo, g.length))
+    tol = 1e-12 if dt == "f64" else 1e-5
+    assert abs(to_host(W)[1] - W_ref) <= tol * W_ref
+    np.testing.assert_allclose(to_host(mom)[4:], m_ref, rtol=tol)
     if dt == "f32":
         # the oracle stepped the FP64 state; the FP32 input differs from it
         # by its rounding, which the (linear, L2-bounded) step carries over
