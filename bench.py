@@ -305,6 +305,18 @@ def sweep_microbench(vp, torch, w, methods, stream, reps=20, warmup=3):
         ms = timed(lambda: g.copy_(f))
         res = {"copy": {"ms": ms, "GBs": 2 * n4 * es / (ms * 1e-3) / 1e9}}
         copy_gbs = res["copy"]["GBs"]
+        # copies with each sweep family's access pattern (the library's
+        # vp_copy_pattern): the bandwidth that pattern reaches here
+        ceilings = {}
+        for pname, pid in (("contiguous", vp.PATTERN_CONTIGUOUS), ("tiles", vp.PATTERN_TILES),
+                           ("segments", vp.PATTERN_SEGMENTS), ("lines", vp.PATTERN_LINES)):
+            for axis in ((0,) if pname == "contiguous" else (0, 1, 2)):
+                pms = timed(lambda: vp.vp_copy_pattern(pid, f, g, axis, stream=stream))
+                torch.cuda.synchronize()
+                assert torch.equal(f, g), f"vp_copy_pattern {pname} axis {axis} is no copy"
+                key = pname if pname == "contiguous" else f"{pname}_{('x1', 'x2', 'v1')[axis]}"
+                ceilings[key] = 2 * n4 * es / (pms * 1e-3) / 1e9
+        res["pattern_copy_GBs"] = ceilings
         for m in methods:
             deg = w.degree if m == "sldg" else -1
             shifts = step_shifts(w, deg)
@@ -317,9 +329,11 @@ def sweep_microbench(vp, torch, w, methods, stream, reps=20, warmup=3):
                     fn = lambda: vp.spline_advect(axis, f, g, sig, stream=stream)
                 ms = timed(fn)
                 gbs = 2 * n4 * es / (ms * 1e-3) / 1e9
+                pkey = sweep_pattern(m, axis)
                 per[("x1", "x2", "v1", "v2")[axis]] = {
                     "us": ms * 1e3, "dof_updates_per_s": n4 / (ms * 1e-3), "alg_GBs": gbs,
-                    "frac_of_peak": gbs / HBM_PEAK_GBS, "frac_of_copy": gbs / copy_gbs}
+                    "frac_of_peak": gbs / HBM_PEAK_GBS, "frac_of_copy": gbs / copy_gbs,
+                    "pattern": pkey, "frac_of_pattern_copy": gbs / ceilings[pkey]}
             per["mean_frac_of_peak"] = float(np.mean([v["frac_of_peak"] for v in per.values()]))
             res[m] = per
         out[dt] = res
@@ -357,6 +371,19 @@ def run_merged(vp, torch, w, dt, methods, steps, every, stream):
         st.close()
         del f, tmp
     return out
+
+
+def sweep_pattern(method, axis, fused=False):
+    """The vp_copy_pattern access pattern of a sweep kernel: row sweeps
+    stream contiguous tiles, spline columns load 64-line tiles, plain SLDG
+    columns run by row segments, and the fused SLDG x2 sweep walks whole
+    lines."""
+    if axis == 3:
+        return "contiguous"
+    name = ("x1", "x2", "v1")[axis]
+    if method == "spline":
+        return f"tiles_{name}"
+    return f"lines_{name}" if fused else f"segments_{name}"
 
 
 def step_shifts(w, degree):
@@ -529,6 +556,13 @@ def main():
 
     if not a.no_microbench:
         out["sweep_microbench"] = sweep_microbench(vp, torch, w, methods, stream)
+        # the dominant kernel against a copy with its own access pattern
+        meth, _, kind = dominant.partition("_sweep_")
+        axis = {"x1": 0, "x2": 1, "v1": 2, "v2": 3, "x2_rho": 1}[kind]
+        pkey = sweep_pattern(meth, axis, fused=kind == "x2_rho")
+        ceil_gbs = out["sweep_microbench"][dt]["pattern_copy_GBs"][pkey]
+        roofline["pattern_copy"] = {"pattern": pkey, "GBs": ceil_gbs,
+                                    "frac": roofline["achieved"] / ceil_gbs}
 
     if not a.no_merged:
         mr = run_merged(vp, torch, w, dt, methods, a.steps, a.diag_every, stream)

@@ -353,6 +353,31 @@ enum {
 VP4D_API vp_status vp_timing_enable(vp_state* st, int enable);
 VP4D_API vp_status vp_timing_read(vp_state* st, double* ms, int64_t* counts);
 
+/*
+ * vp_copy_pattern -- a measurement aid: copies f_in to f_out (same shape,
+ * dtype dt) with the global-memory access pattern of one family of sweep
+ * kernels and no arithmetic, so that a sweep's rate can be read against
+ * the bandwidth its own access pattern reaches on the device.
+ *
+ *   VP_PATTERN_CONTIGUOUS  flat, 16 bytes per lane (row sweeps; axis ignored)
+ *   VP_PATTERN_TILES       lines along `axis` in tiles of 64 adjacent lines,
+ *                          a quarter line per thread, its loads and then its
+ *                          stores (spline column sweeps); dims[axis] <= 384
+ *   VP_PATTERN_SEGMENTS    lines along `axis` by segments of 24 rows, one
+ *                          thread per (segment, line), blocks in memory order
+ *                          (row-segment SLDG sweeps)
+ *   VP_PATTERN_LINES       lines along `axis`, one thread per whole line,
+ *                          rows in memory order (the fused SLDG x2 sweep)
+ *   axis       0..2 for the strided patterns.
+ *   f_in/out   device, 16-byte aligned, not overlapping (VP_ERR_ALIAS).
+ */
+enum {
+    VP_PATTERN_CONTIGUOUS = 0, VP_PATTERN_TILES = 1, VP_PATTERN_SEGMENTS = 2,
+    VP_PATTERN_LINES = 3
+};
+VP4D_API vp_status vp_copy_pattern(int pattern, vp_dtype dt, const int64_t dims[4], int axis,
+                          const void* f_in, void* f_out, void* stream);
+
 /* Thread-local description of the last non-OK status ("" if none). */
 VP4D_API const char* vp_last_error(void);
 

@@ -341,5 +341,21 @@ class VPState:
         return {TIMER_NAMES[i]: (ms[i], cnt[i]) for i in range(_lib.VP_TIMER_COUNT)}
 
 
+PATTERN_CONTIGUOUS = _lib.VP_PATTERN_CONTIGUOUS
+PATTERN_TILES = _lib.VP_PATTERN_TILES
+PATTERN_SEGMENTS = _lib.VP_PATTERN_SEGMENTS
+PATTERN_LINES = _lib.VP_PATTERN_LINES
+
+
+def vp_copy_pattern(pattern, f_in, f_out, axis=0, stream=None):
+    """f_out = f_in with the access pattern of a sweep family (C ABI
+    ``vp_copy_pattern``): a bandwidth reference for the sweeps."""
+    if f_in.dtype != f_out.dtype or f_in.shape != f_out.shape:
+        raise ValueError("f_in and f_out must match in shape and dtype")
+    _check("vp_copy_pattern", lib().vp_copy_pattern(
+        int(pattern), _dtype(f_in), _dims(f_in), int(axis), _dev(f_in, "f_in"),
+        _dev(f_out, "f_out"), _stream(stream)))
+
+
 def version():
     return lib().vp_version().decode()

@@ -23,6 +23,10 @@ VP_F32 = 0
 VP_F64 = 1
 VP_TIMER_COUNT = 7
 VP_POISSON_NOALLOC_MAX_POINTS = 512 * 512
+VP_PATTERN_CONTIGUOUS = 0
+VP_PATTERN_TILES = 1
+VP_PATTERN_SEGMENTS = 2
+VP_PATTERN_LINES = 3
 TIMER_NAMES = ("sweep_x1", "sweep_x2", "sweep_v1", "sweep_v2", "field", "diag",
                "sweep_x2_rho")
 
@@ -81,6 +85,8 @@ SIGNATURES = {
     "vp_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "vp_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int64)]),
+    "vp_copy_pattern": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64x4, ctypes.c_int, _vp,
+                                       _vp, _vp]),
     "vp_last_error": (ctypes.c_char_p, []),
     "vp_version": (ctypes.c_char_p, []),
 }

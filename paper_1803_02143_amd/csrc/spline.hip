@@ -716,6 +716,29 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                 if (e0 + u * kBlock < cnt) buf[pos[u]] = v[u];
         }
     }
+    // shift derivative: the lam values of this wavefront's rows (the row
+    // passes below: rows r0 + u kWaves, column blocks of 64) loaded before the
+    // solve, so that they arrive while it runs; tiles with more rows or
+    // longer rows than the registers hold load lam after the solve
+    constexpr int kPfPass = sizeof(T) == 8 ? 2 : 4;   // passes of kU rows
+    constexpr int kPfCol = 2;                         // column blocks
+    const bool pf = MODE == kDshift && nr <= kPfPass * kU * kWaves && n <= kPfCol * 64;
+    T lpf[MODE == kDshift ? kPfPass * kU * kPfCol : 1];
+    if (MODE == kDshift && pf) {
+#pragma unroll
+        for (int p = 0; p < kPfPass; ++p)
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+#pragma unroll
+                for (int c = 0; c < kPfCol; ++c) {
+                    const int r = wave + (p * kU + u) * kWaves;
+                    const int i = c * 64 + lane;
+                    // (clamped: every load in range, unused values ignored)
+                    const int rr = r < nr ? r : nr - 1;
+                    const int ii = i < n ? i : n - 1;
+                    lpf[(p * kU + u) * kPfCol + c] = lam[(row0 + rr) * n + ii];
+                }
+    }
     if (threadIdx.x < nr) {
         const int r = threadIdx.x;
         int s;
@@ -858,6 +881,40 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     // kU row sums of the wavefront are reduced together (reduce-scatter).
     // (Few rows per pass keep the registers, and so the occupancy that hides
     // the lam loads, at the level of the forward sweep.)
+    if (pf) {
+#pragma unroll
+        for (int p = 0; p < kPfPass; ++p) {
+            const int r0 = wave + p * kU * kWaves;
+            if (r0 >= nr) break;
+            double acc[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                acc[u] = 0.0;
+                const int r = r0 + u * kWaves;
+                if (r < nr) {
+                    const T* row = buf + r * ld;
+                    const T w0 = wts[4 * r + 0], w1 = wts[4 * r + 1];
+                    const T w2 = wts[4 * r + 2], w3 = wts[4 * r + 3];
+                    const int s = sh[r];
+#pragma unroll
+                    for (int c = 0; c < kPfCol; ++c) {
+                        const int i = c * 64 + lane;
+                        if (i < n) {
+                            const int j0 = first_tap(i, s, n);
+                            const int j1 = next_idx(j0, n), j2 = next_idx(j1, n);
+                            const int j3 = next_idx(j2, n);
+                            const T v = fma(w3, row[j3], fma(w2, row[j2], fma(w1, row[j1], w0 * row[j0])));
+                            acc[u] = fma(static_cast<double>(lpf[(p * kU + u) * kPfCol + c]),
+                                         static_cast<double>(v), acc[u]);
+                        }
+                    }
+                }
+            }
+            const double a = group_reduce_scatter<kU, 64>(acc, lane);
+            if (lane < kU && r0 + lane * kWaves < nr) g[row0 + r0 + lane * kWaves] = a;
+        }
+        return;
+    }
     for (int r0 = wave; r0 < nr; r0 += kWaves * kU) {
         double acc[kU];
 #pragma unroll

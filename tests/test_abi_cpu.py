@@ -157,3 +157,19 @@ def test_noalloc_poisson_rejects_before_touching_the_device():
     assert lib.vp_poisson_noalloc(9, 6, 6, 1.0, 1.0, pa, pb, pc, None, None) == \
         L.VP_ERR_UNSUPPORTED
 
+
+
+def test_copy_pattern_argument_errors():
+    L, lib = _lib()
+    dims = L.i64x4((6, 6, 6, 6))
+    far = [ctypes.c_void_p(k << 32) for k in (1, 2)]
+    assert lib.vp_copy_pattern(7, L.VP_F64, dims, 0, *far, None) == L.VP_ERR_ARG
+    assert lib.vp_copy_pattern(L.VP_PATTERN_TILES, L.VP_F64, dims, 3, *far, None) == L.VP_ERR_ARG
+    assert lib.vp_copy_pattern(L.VP_PATTERN_LINES, L.VP_F64, dims, 0, far[0], far[0], None) == \
+        L.VP_ERR_ALIAS
+    odd = ctypes.c_void_p((2 << 32) + 8)
+    assert lib.vp_copy_pattern(L.VP_PATTERN_CONTIGUOUS, L.VP_F64, dims, 0, far[0], odd, None) == \
+        L.VP_ERR_ARG
+    long_lines = L.i64x4((400, 2, 2, 2))
+    assert lib.vp_copy_pattern(L.VP_PATTERN_TILES, L.VP_F32, long_lines, 0, *far, None) == \
+        L.VP_ERR_UNSUPPORTED

@@ -274,3 +274,19 @@ def test_init_parity(kind, form, degree):
                                   None if degree < 0 else degree, eps, k, v0,
                                   form=form or "sum")
     assert rel_l2(to_host(f), ref) < 1e-14
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("dims", [(7, 5, 9, 13), (4, 6, 96, 256), (3, 130, 2, 128)])
+def test_copy_patterns_are_exact_copies(dt, dims):
+    # the bandwidth references of the bench copy every element (ragged
+    # tiles, segments and flat tails included)
+    vp = require_gpu()
+    f = to_dev(random_field(dims, seed=3), dt)
+    for pid in (vp.PATTERN_CONTIGUOUS, vp.PATTERN_TILES, vp.PATTERN_SEGMENTS, vp.PATTERN_LINES):
+        for axis in ((0,) if pid == vp.PATTERN_CONTIGUOUS else (0, 1, 2)):
+            announce(f"vp_copy_pattern {pid} axis {axis} {dt} {dims}")
+            g = torch.full_like(f, float("nan"))
+            vp.vp_copy_pattern(pid, f, g, axis)
+            torch.cuda.synchronize()
+            assert torch.equal(f, g), (pid, axis)
