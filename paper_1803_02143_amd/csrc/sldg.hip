@@ -281,21 +281,27 @@ sldg_col(const T* __restrict__ fin, T* __restrict__ fout,
 // accesses advance through memory in block order stream like a plain copy,
 // where one thread per whole line (sldg_col) keeps every row of the array
 // in flight at the same time.
-template <int M, typename T, bool ADJ, int C, bool BAND>
+//
+// With J > 1 (band blocks only) a thread takes J adjacent columns that share
+// the shift (a shift that does not depend on the fastest axis), loaded as
+// one vector per row: workgroups of 256 J columns and C = 8 / J cells, the
+// same outputs per operator build over a shorter band of rows.
+template <int M, typename T, bool ADJ, int C, bool BAND, int J>
 __global__ void __launch_bounds__(kBlock)
 sldg_seg(const T* __restrict__ fin, T* __restrict__ fout,
          const double* __restrict__ shift, ShiftMap sm, int64_t outer, int nc,
          int64_t inner, int nseg, NodeBasis basis) {
+    static_assert(J == 1 || BAND, "stacked columns need band blocks");
     int64_t o, k;
     int q;
     if (BAND) {
-        const int64_t nkb = inner / kBlock;
+        const int64_t nkb = inner / (J * kBlock);
         const int64_t b = blockIdx.x;
         const int64_t kb = b % nkb;
         const int64_t rest = b / nkb;
         q = static_cast<int>(rest % nseg);
         o = rest / nseg;
-        k = kb * kBlock + threadIdx.x;
+        k = (kb * kBlock + threadIdx.x) * J;
     } else {
         q = static_cast<int>(blockIdx.x % nseg);
         const int64_t line = static_cast<int64_t>(blockIdx.x / nseg) * kBlock + threadIdx.x;
@@ -316,16 +322,47 @@ sldg_seg(const T* __restrict__ fin, T* __restrict__ fout,
     int c = ADJ ? i0 + s : i0 - s - 1;
     c += c < 0 ? nc : 0;
     c -= c >= nc ? nc : 0;
-    T u[C + 1][M];
+    if constexpr (J == 1) {
+        T u[C + 1][M];
 #pragma unroll
-    for (int j = 0; j <= C; ++j) {
+        for (int j = 0; j <= C; ++j) {
 #pragma unroll
-        for (int l = 0; l < M; ++l) u[j][l] = src[c * cs + l * inner];
-        c = c + 1 == nc ? 0 : c + 1;
+            for (int l = 0; l < M; ++l) u[j][l] = src[c * cs + l * inner];
+            c = c + 1 == nc ? 0 : c + 1;
+        }
+#pragma unroll
+        for (int j = 0; j < C; ++j)
+            if (i0 + j < nc) sldg_cell<M, T>(A, B, u[j], u[j + 1], dst + (i0 + j) * cs, inner);
+    } else {
+        using VJ = T __attribute__((ext_vector_type(J)));
+        VJ u[C + 1][M];
+#pragma unroll
+        for (int j = 0; j <= C; ++j) {
+#pragma unroll
+            for (int l = 0; l < M; ++l)
+                u[j][l] = *reinterpret_cast<const VJ*>(src + c * cs + l * inner);
+            c = c + 1 == nc ? 0 : c + 1;
+        }
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            if (i0 + j < nc) {
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    VJ acc;
+#pragma unroll
+                    for (int e = 0; e < J; ++e) {
+                        T a = T(0);
+#pragma unroll
+                        for (int l = 0; l < M; ++l) a = fma(A[m][l], u[j][l][e], a);
+#pragma unroll
+                        for (int l = 0; l < M; ++l) a = fma(B[m][l], u[j + 1][l][e], a);
+                        acc[e] = a;
+                    }
+                    __builtin_nontemporal_store(acc, reinterpret_cast<VJ*>(dst + (i0 + j) * cs + m * inner));
+                }
+            }
+        }
     }
-#pragma unroll
-    for (int j = 0; j < C; ++j)
-        if (i0 + j < nc) sldg_cell<M, T>(A, B, u[j], u[j + 1], dst + (i0 + j) * cs, inner);
 }
 
 // The x2 sweep with its output density formed on the way (forward only).
@@ -628,10 +665,22 @@ sldg_row(const T* __restrict__ fin, T* __restrict__ fout,
     }
 }
 
+// Adjacent columns per thread of the segmented sweep (J) when the shift
+// does not depend on the fastest axis: 16-byte loads, and a band of 8 / J
+// cells; 1 when the grid does not divide into workgroups of 256 J columns.
+int seg_columns(vp_dtype dt, int axis, const int64_t dims[4], bool shift_shared_v2) {
+    if (axis > 2 || !shift_shared_v2) return 1;
+    int64_t inner = 1;
+    for (int d = axis + 1; d < 4; ++d) inner *= dims[d];
+    int J = dt == VP_F64 ? 2 : 4;
+    while (J > 1 && (dims[3] % J || (inner / J) % kBlock)) J /= 2;
+    return J;
+}
+
 template <int M, typename T, bool ADJ>
 vp_status launch_sldg(int axis, const int64_t dims[4], const void* fin,
                       void* fout, const double* shift, const ShiftMap& sm,
-                      hipStream_t st) {
+                      hipStream_t st, int jcols) {
     const NodeBasis& b = node_basis(M - 1);
     int64_t outer = 1, inner = 1;
     for (int d = 0; d < axis; ++d) outer *= dims[d];
@@ -639,6 +688,22 @@ vp_status launch_sldg(int axis, const int64_t dims[4], const void* fin,
     const int nc = static_cast<int>(dims[axis] / M);
     const T* in = static_cast<const T*>(fin);
     T* out = static_cast<T*>(fout);
+    if (axis < 3 && jcols > 1) {
+        // (M <= 3: a vector of J columns per row of the segment)
+        const int C = kSegCells / jcols;
+        const int nseg = (nc + C - 1) / C;
+        const int64_t nblk = outer * nseg * (inner / (jcols * kBlock));
+        if constexpr (M <= 3) {
+            if (nblk < (int64_t(1) << 31)) {
+                const unsigned g = static_cast<unsigned>(nblk);
+                if (jcols == 2)
+                    sldg_seg<M, T, ADJ, kSegCells / 2, true, 2><<<g, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, nseg, b);
+                else
+                    sldg_seg<M, T, ADJ, kSegCells / 4, true, 4><<<g, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, nseg, b);
+                return check_launch("sldg_seg");
+            }
+        }
+    }
     if (axis < 3) {
         constexpr int C = kSegCells;
         const int nseg = (nc + C - 1) / C;
@@ -648,9 +713,9 @@ vp_status launch_sldg(int axis, const int64_t dims[4], const void* fin,
         if (nblk < (int64_t(1) << 31)) {
             const unsigned g = static_cast<unsigned>(nblk);
             if (band)
-                sldg_seg<M, T, ADJ, C, true><<<g, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, nseg, b);
+                sldg_seg<M, T, ADJ, C, true, 1><<<g, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, nseg, b);
             else
-                sldg_seg<M, T, ADJ, C, false><<<g, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, nseg, b);
+                sldg_seg<M, T, ADJ, C, false, 1><<<g, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, nseg, b);
             return check_launch("sldg_seg");
         }
         const unsigned grid = blocks_for(outer * inner, kBlock);
@@ -683,14 +748,14 @@ vp_status launch_sldg(int axis, const int64_t dims[4], const void* fin,
 template <typename T, bool ADJ>
 vp_status dispatch_degree(int degree, int axis, const int64_t dims[4],
                           const void* fin, void* fout, const double* shift,
-                          const ShiftMap& sm, hipStream_t st) {
+                          const ShiftMap& sm, hipStream_t st, int jcols) {
     switch (degree) {
-        case 0: return launch_sldg<1, T, ADJ>(axis, dims, fin, fout, shift, sm, st);
-        case 1: return launch_sldg<2, T, ADJ>(axis, dims, fin, fout, shift, sm, st);
-        case 2: return launch_sldg<3, T, ADJ>(axis, dims, fin, fout, shift, sm, st);
-        case 3: return launch_sldg<4, T, ADJ>(axis, dims, fin, fout, shift, sm, st);
-        case 4: return launch_sldg<5, T, ADJ>(axis, dims, fin, fout, shift, sm, st);
-        case 5: return launch_sldg<6, T, ADJ>(axis, dims, fin, fout, shift, sm, st);
+        case 0: return launch_sldg<1, T, ADJ>(axis, dims, fin, fout, shift, sm, st, jcols);
+        case 1: return launch_sldg<2, T, ADJ>(axis, dims, fin, fout, shift, sm, st, jcols);
+        case 2: return launch_sldg<3, T, ADJ>(axis, dims, fin, fout, shift, sm, st, jcols);
+        case 3: return launch_sldg<4, T, ADJ>(axis, dims, fin, fout, shift, sm, st, jcols);
+        case 4: return launch_sldg<5, T, ADJ>(axis, dims, fin, fout, shift, sm, st, jcols);
+        case 5: return launch_sldg<6, T, ADJ>(axis, dims, fin, fout, shift, sm, st, jcols);
         default: return set_error(VP_ERR_UNSUPPORTED, "degree %d", degree);
     }
 }
@@ -938,13 +1003,17 @@ vp_status sldg_advect_impl(int axis, int degree, vp_dtype dt,
                            const double* shift, const int64_t shift_stride[4],
                            hipStream_t st, bool adjoint) {
     const ShiftMap sm = make_shift_map(axis, dims, shift_stride);
+    int jc = degree <= 2 ? seg_columns(dt, axis, dims, shift_stride[3] == 0) : 1;
+    // (vector loads and stores of J values: both arrays aligned to them)
+    const uintptr_t al = static_cast<uintptr_t>(jc) * dtype_size(dt);
+    if ((reinterpret_cast<uintptr_t>(f_in) | reinterpret_cast<uintptr_t>(f_out)) % al) jc = 1;
     if (dt == VP_F64)
         return adjoint
-                   ? dispatch_degree<double, true>(degree, axis, dims, f_in, f_out, shift, sm, st)
-                   : dispatch_degree<double, false>(degree, axis, dims, f_in, f_out, shift, sm, st);
+                   ? dispatch_degree<double, true>(degree, axis, dims, f_in, f_out, shift, sm, st, jc)
+                   : dispatch_degree<double, false>(degree, axis, dims, f_in, f_out, shift, sm, st, jc);
     return adjoint
-               ? dispatch_degree<float, true>(degree, axis, dims, f_in, f_out, shift, sm, st)
-               : dispatch_degree<float, false>(degree, axis, dims, f_in, f_out, shift, sm, st);
+               ? dispatch_degree<float, true>(degree, axis, dims, f_in, f_out, shift, sm, st, jc)
+               : dispatch_degree<float, false>(degree, axis, dims, f_in, f_out, shift, sm, st, jc);
 }
 
 int sldg_rho_stack(vp_dtype dt, int degree, const int64_t dims[4]) {

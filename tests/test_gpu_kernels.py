@@ -56,6 +56,35 @@ def test_sldg_advect_parity(cells, degree, dt):
         assert_close(to_host(out), ref, dt, f"axis {axis}")
 
 
+@pytest.mark.parametrize("cells,degree", [((2, 4, 8, 32), 2), ((4, 2, 8, 32), 1)])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_sldg_advect_parity_shift_shared_along_v2(cells, degree, dt):
+    # shifts that do not depend on v2 (as in the x1 sweep of a step): a
+    # thread takes 2 or 4 adjacent v2 columns with vector loads and stores
+    vp = require_gpu()
+    m = degree + 1
+    dims = tuple(c * m for c in cells)
+    f = random_field(dims, seed=7 + degree)
+    fin = to_dev(f, dt)
+    fr = to_host(fin)
+    rng = np.random.default_rng(8)
+    for axis in range(3):
+        shape = list(dims)
+        shape[axis] = 1
+        shape[3] = 1
+        sig = rng.uniform(-2.5, 2.5, size=shape)
+        sig.flat[0] = -1e-17
+        announce(f"sldg_advect shared-v2 shift {cells} degree={degree} {dt} axis={axis}")
+        out = torch.empty_like(fin)
+        vp.sldg_advect(axis, degree, fin, out, to_dev(sig))
+        assert_close(to_host(out), sldg.sweep(fr, axis, sig, degree), dt, f"axis {axis}")
+        lam = torch.empty_like(fin)
+        vp.sldg_advect_adjoint(axis, degree, fin, lam, to_dev(sig))
+        from oracle import adjoint as oadj
+        assert_close(to_host(lam), oadj.sldg_sweep_adjoint(fr, axis, sig, degree), dt,
+                     f"adjoint axis {axis}")
+
+
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_sldg_integer_shift_is_exact_permutation(dt):
     vp = require_gpu()
