@@ -396,3 +396,41 @@ def test_merged_run_parity_table1_64():
     assert np.max(np.abs(to_host(W) - Wr) / Wr) <= 1e-12
     np.testing.assert_allclose(to_host(mom).reshape(2, 4), mr, rtol=1e-12)
     st.close()
+
+
+@pytest.mark.parametrize("method", ["sldg", "spline"])
+def test_landau96_whole_run_against_stored_oracle_trace(method):
+    # the 96^4 Landau run of Sec. 4 (tau = 0.05, 200 Strang steps, FP64):
+    # W(t_m) of every state and its mass, L1, L2 and kinetic energy against
+    # the oracle's run (tests/golden/make_landau96_golden.py), whole run at
+    # 1e-10 relative
+    import json
+    import os
+    vp = require_gpu()
+    w = workload("landau_32")
+    path = os.path.join(os.path.dirname(__file__), "golden", f"landau96_trace_{method}.json")
+    with open(path) as fh:
+        gold = json.load(fh)
+    assert tuple(gold["dims"]) == w.dofs and gold["steps"] == w.steps and gold["tau"] == w.dt
+    st = vp.VPState(vp.METHOD_SLDG if method == "sldg" else vp.METHOD_SPLINE, w.degree,
+                    torch.float64, w.dofs, w.lo, w.length)
+    f = torch.empty(w.dofs, dtype=torch.float64, device="cuda")
+    vp.vp_init(vp.IC_LANDAU, w.eps, w.k, 0.0, w.degree if method == "sldg" else -1, f,
+               w.lo, w.length)
+    tmp = torch.empty_like(f)
+    W = torch.empty(w.steps + 1, dtype=torch.float64, device="cuda")
+    mom = torch.empty(4 * (w.steps + 1), dtype=torch.float64, device="cuda")
+    announce(f"96^4 Landau {method}: {w.steps} steps against the oracle trace")
+    st.step(f, tmp, w.steps, w.dt, W, mom)
+    Wd = to_host(W)
+    md = to_host(mom).reshape(-1, 4)
+    st.close()
+    Wr = np.array(gold["W"])
+    mr = np.array(gold["moments"])
+    err_W = np.abs(Wd - Wr) / np.abs(Wr)
+    announce(f"max rel diff of W over the run {err_W.max():.3e} (step {int(err_W.argmax())})")
+    assert err_W.max() <= 1e-10, (err_W.max(), int(err_W.argmax()))
+    err_m = np.abs(md - mr) / np.abs(mr)
+    assert err_m.max() <= 1e-10, err_m.max(axis=0)
+    # mass conservation to round-off over the whole run
+    assert np.max(np.abs(md[:, 0] - md[0, 0])) <= 1e-12 * md[0, 0]
