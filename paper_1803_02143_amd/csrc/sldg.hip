@@ -688,6 +688,12 @@ vp_status launch_sldg(int axis, const int64_t dims[4], const void* fin,
     const int nc = static_cast<int>(dims[axis] / M);
     const T* in = static_cast<const T*>(fin);
     T* out = static_cast<T*>(fout);
+    // Band blocks (lines of whole workgroups of columns) pay off while one
+    // row of the array is short: at 96^4 (7 MB rows along x1) they beat one
+    // thread per whole line, at 192^4 and 288^4 (28-95 MB rows) they lose
+    // to it; lines with fewer than 256 columns always run by segments.
+    const bool band_ok = static_cast<size_t>(inner) * sizeof(T) <= (size_t(16) << 20);
+    if (!band_ok) jcols = 1;
     if (axis < 3 && jcols > 1) {
         // (M <= 3: a vector of J columns per row of the segment)
         const int C = kSegCells / jcols;
@@ -710,7 +716,7 @@ vp_status launch_sldg(int axis, const int64_t dims[4], const void* fin,
         const bool band = inner % kBlock == 0;
         const int64_t nblk = band ? outer * nseg * (inner / kBlock)
                                   : static_cast<int64_t>(blocks_for(outer * inner, kBlock)) * nseg;
-        if (nblk < (int64_t(1) << 31)) {
+        if ((band_ok || !band) && nblk < (int64_t(1) << 31)) {
             const unsigned g = static_cast<unsigned>(nblk);
             if (band)
                 sldg_seg<M, T, ADJ, C, true, 1><<<g, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, nseg, b);
@@ -718,6 +724,7 @@ vp_status launch_sldg(int axis, const int64_t dims[4], const void* fin,
                 sldg_seg<M, T, ADJ, C, false, 1><<<g, kBlock, 0, st>>>(in, out, shift, sm, outer, nc, inner, nseg, b);
             return check_launch("sldg_seg");
         }
+        // one thread per whole line
         const unsigned grid = blocks_for(outer * inner, kBlock);
         switch (axis) {
             case 0:
