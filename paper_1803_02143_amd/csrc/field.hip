@@ -417,11 +417,12 @@ vp_status launch_reduce(bool diag, const int64_t dims[4], const void* f,
 
 vp_status moments_from_parts_impl(const double* mom_part, int64_t nparts, double* chunk,
                                   double* out4, hipStream_t st) {
-    // one block reads at most a few hundred kB quickly; beyond that the parts
-    // are first added in up to kMaxChunks contiguous chunks by as many blocks
-    if (nparts > 4 * kFinalBlock && chunk) {
-        const int64_t nb = std::min<int64_t>(kMaxChunks, (nparts + 4 * kFinalBlock - 1) / (4 * kFinalBlock));
-        const int64_t per = (nparts + nb - 1) / nb;
+    // one block adds a few thousand parts quickly (two per thread); beyond
+    // that the parts are first added in contiguous chunks of one part per
+    // thread (more per thread only past kMaxChunks chunks), whose loads are
+    // all in flight at once
+    if (nparts > 2 * kFinalBlock && chunk) {
+        const int64_t per = std::max<int64_t>(kChunkBlock, (nparts + kMaxChunks - 1) / kMaxChunks);
         const int64_t used = (nparts + per - 1) / per;
         moments_chunks<<<static_cast<unsigned>(used), kChunkBlock, 0, st>>>(mom_part, nparts,
                                                                            per, chunk);

@@ -372,13 +372,16 @@ sldg_seg(const T* __restrict__ fin, T* __restrict__ fout,
 // every lane of a wavefront on the same cell: output i is fed by input
 // cells (l0 + i, l0 + i + 1) mod n_c with l0 = n_c - 1 - s, which lanes load
 // from their own (shift-dependent) rows.  A lane first adds W3 W4 f_out
-// over its J columns, then the wavefront reduce-scatters those per-cell
-// values (one exchange per J columns) while the next cells' loads are in
-// flight; the four wavefronts' sums meet in LDS, and each workgroup writes
-// the partial density of its 256 J velocity columns (N3 / J N4 must be a
-// multiple of the workgroup size).  Every input cell is loaded once.  (A
-// row-segmented form, as for the plain sweeps, ran slower here: its
-// reductions come after all of its loads, with nothing left to overlap.)
+// over its J columns; the wavefront then sums those per-cell values four at
+// a time (`wave_sum4_rows`: a batch of CU cells gives CU (l+1) values, a
+// multiple of four), and the four wavefronts' sums meet in LDS, where each
+// workgroup writes the partial density of its 256 J velocity columns
+// (N3 N4 / J must be a multiple of the workgroup size, so that a workgroup
+// stays within one x1 index).  Every input cell is loaded once.  The x1
+// plane is read and written as a buffer (it must hold less than 4 GB): the
+// loads of a cell share one per-lane byte offset, the stores the lane's
+// column offset, with the rest of each address uniform.  (A row-segmented form, as for the plain sweeps, ran slower here:
+// its reductions come after all of its loads, with nothing left to overlap.)
 template <int M, typename T, int J, bool MOM>
 __global__ void __launch_bounds__(kBlock)
 sldg_col_rho(const T* __restrict__ fin, T* __restrict__ fout,
@@ -387,10 +390,9 @@ sldg_col_rho(const T* __restrict__ fin, T* __restrict__ fout,
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = nc * M;
     double* rp = reinterpret_cast<double*>(smem);   // [kBlock / 64][N]
-    const int64_t tpo = inner / J;                  // threads per x1 index
-    const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    const int64_t o = gid / tpo;
-    const int t = static_cast<int>(gid - o * tpo);
+    const int bpo = static_cast<int>(inner / (J * kBlock));   // workgroups per x1 index
+    const int o = static_cast<int>(blockIdx.x) / bpo;
+    const int t = (static_cast<int>(blockIdx.x) - o * bpo) * kBlock + static_cast<int>(threadIdx.x);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int v1b = t / rf.n4;                      // J v1 nodes v1b J .. v1b J + J - 1
@@ -406,18 +408,27 @@ sldg_col_rho(const T* __restrict__ fin, T* __restrict__ fout,
     T A[M][M], B[M][M];
     sldg_operator<M, T>(basis, shift[shift_offset(sm, o, k0)], nc, s, A, B);
     const int64_t cs = static_cast<int64_t>(M) * inner;
-    const T* __restrict__ src = fin + o * nc * cs + k0;
-    T* __restrict__ dst = fout + o * nc * cs + k0;
+    // the x1 plane o of input and output as buffers; per lane one byte offset
+    const uint32_t pb = static_cast<uint32_t>(nc * cs * sizeof(T));
+    const __amdgpu_buffer_rsrc_t rin = buffer_of(fin + static_cast<int64_t>(o) * nc * cs, pb);
+    const __amdgpu_buffer_rsrc_t rout = buffer_of(fout + static_cast<int64_t>(o) * nc * cs, pb);
+    const uint32_t kb = static_cast<uint32_t>(k0 * sizeof(T));     // lane's byte offset
+    const uint32_t cb = static_cast<uint32_t>(cs * sizeof(T));     // cell stride, bytes
+    // input (cell c, dof l, column j); output (cell i, dof m, column j)
+    auto ld = [&](int c, int l, int j) -> T {
+        return buffer_load<T>(rin, static_cast<uint32_t>(c) * cb + kb,
+                              static_cast<uint32_t>((l * inner + j * js) * sizeof(T)));
+    };
+    auto st = [&](int i, int m, int j, T v) {
+        buffer_store_nt<T>(v, rout, kb, static_cast<uint32_t>((i * cs + m * inner + j * js) * sizeof(T)));
+    };
 
     const int l0 = nc - 1 - s;
-    T first[J][M], prev[J][M];
+    T prev[J][M];
 #pragma unroll
     for (int j = 0; j < J; ++j)
 #pragma unroll
-        for (int l = 0; l < M; ++l) {
-            first[j][l] = src[l0 * cs + l * inner + j * js];
-            prev[j][l] = first[j][l];
-        }
+        for (int l = 0; l < M; ++l) prev[j][l] = ld(l0, l, j);
     int rc = l0 + 1 == nc ? 0 : l0 + 1;   // next input cell to load
     // moments: sums over the thread's columns of W2 W3 f, W2 W3 |f|,
     // W2 W3 f^2 and W2 W3 |v|^2 f (W4 and W1 are applied at the end)
@@ -436,73 +447,8 @@ sldg_col_rho(const T* __restrict__ fin, T* __restrict__ fout,
             vv[j] = a1 * a1 + a2 * a2;
         }
     }
-    // cells whose loads are in flight together (about 12 loads, an even
-    // number of cells when more than one), reduced two at a time
-    constexpr int CU0 = 12 / (J * M);
-    constexpr int CU = CU0 >= 2 ? (CU0 & ~1) : (J * M >= 12 ? 1 : 2);
-    constexpr int P = CU >= 2 ? 2 : 1;
-    static_assert(CU % P == 0, "whole reduction groups per batch");
-    constexpr int V = P * M <= 4 ? 4 : (P * M <= 8 ? 8 : 16);
-    int i = 0;
-    for (; i + CU <= nc - 1; i += CU) {
-        T cur[CU][J][M];
-#pragma unroll
-        for (int u = 0; u < CU; ++u) {
-            int c = rc + u;
-            c -= c >= nc ? nc : 0;
-#pragma unroll
-            for (int j = 0; j < J; ++j)
-#pragma unroll
-                for (int l = 0; l < M; ++l) cur[u][j][l] = src[c * cs + l * inner + j * js];
-        }
-#pragma unroll
-        for (int h = 0; h < CU; h += P) {
-            double vals[V];
-#pragma unroll
-            for (int q = 0; q < V; ++q) vals[q] = 0.0;
-#pragma unroll
-            for (int u = h; u < h + P; ++u) {
-#pragma unroll
-                for (int j = 0; j < J; ++j) {
-#pragma unroll
-                    for (int m = 0; m < M; ++m) {
-                        T acc = T(0);
-#pragma unroll
-                        for (int l = 0; l < M; ++l) acc = fma(A[m][l], prev[j][l], acc);
-#pragma unroll
-                        for (int l = 0; l < M; ++l) acc = fma(B[m][l], cur[u][j][l], acc);
-                        put_out(&dst[(i + u) * cs + m * inner + j * js], acc);
-                        const double ov = static_cast<double>(acc);
-                        vals[(u - h) * M + m] = fma(wk[j], ov, vals[(u - h) * M + m]);
-                        if (MOM) {
-                            const double wv = w2[m] * w3[j];
-                            s_m = fma(wv, ov, s_m);
-                            s_a = fma(wv, fabs(ov), s_a);
-                            s_q = fma(wv * ov, ov, s_q);
-                            s_k = fma(wv * vv[j], ov, s_k);
-                        }
-                    }
-#pragma unroll
-                    for (int l = 0; l < M; ++l) prev[j][l] = cur[u][j][l];
-                }
-            }
-            const double r = group_reduce_scatter<V, 64>(vals, lane);
-            if (lane < P * M) rp[wave * N + (i + h) * M + lane] = r;
-        }
-        rc += CU;
-        rc -= rc >= nc ? nc : 0;
-    }
-    constexpr int VT = M <= 4 ? 4 : 8;
-    for (; i < nc; ++i) {
-        T cur[J][M];
-#pragma unroll
-        for (int j = 0; j < J; ++j)
-#pragma unroll
-            for (int l = 0; l < M; ++l)
-                cur[j][l] = i < nc - 1 ? src[rc * cs + l * inner + j * js] : first[j][l];
-        double vals[VT];
-#pragma unroll
-        for (int q = 0; q < VT; ++q) vals[q] = 0.0;
+    // output cell i from the thread's values, its weighted sums into vals
+    auto cell = [&](int i, const T (&cur)[J][M], double* vals) {
 #pragma unroll
         for (int j = 0; j < J; ++j) {
 #pragma unroll
@@ -512,7 +458,7 @@ sldg_col_rho(const T* __restrict__ fin, T* __restrict__ fout,
                 for (int l = 0; l < M; ++l) acc = fma(A[m][l], prev[j][l], acc);
 #pragma unroll
                 for (int l = 0; l < M; ++l) acc = fma(B[m][l], cur[j][l], acc);
-                put_out(&dst[i * cs + m * inner + j * js], acc);
+                st(i, m, j, acc);
                 const double ov = static_cast<double>(acc);
                 vals[m] = fma(wk[j], ov, vals[m]);
                 if (MOM) {
@@ -526,8 +472,59 @@ sldg_col_rho(const T* __restrict__ fin, T* __restrict__ fout,
 #pragma unroll
             for (int l = 0; l < M; ++l) prev[j][l] = cur[j][l];
         }
-        const double r = group_reduce_scatter<VT, 64>(vals, lane);
-        if (lane < M) rp[wave * N + i * M + lane] = r;
+    };
+    // cells whose loads are in flight together: about 12 loads, and whole
+    // groups of four values to sum (CU (l+1) a multiple of 4)
+    constexpr int CU4 = M % 4 == 0 ? 1 : (M % 2 == 0 ? 2 : 4);
+    constexpr int CUW = 12 / (J * M);
+    constexpr int CU = CUW > CU4 ? (CUW / CU4) * CU4 : CU4;
+    constexpr int NV = CU * M;
+    static_assert(NV % 4 == 0, "whole groups of four values");
+    int i = 0;
+    for (; i + CU <= nc - 1; i += CU) {
+        T cur[CU][J][M];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            int c = rc + u;
+            c -= c >= nc ? nc : 0;
+#pragma unroll
+            for (int j = 0; j < J; ++j)
+#pragma unroll
+                for (int l = 0; l < M; ++l) cur[u][j][l] = ld(c, l, j);
+        }
+        double vals[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) vals[q] = 0.0;
+#pragma unroll
+        for (int u = 0; u < CU; ++u) cell(i + u, cur[u], vals + u * M);
+#pragma unroll
+        for (int g = 0; g < NV / 4; ++g) {
+            const double r = wave_sum4_rows(vals[4 * g], vals[4 * g + 1], vals[4 * g + 2], vals[4 * g + 3]);
+            if ((lane & 15) == 0) rp[wave * N + i * M + 4 * g + (lane >> 4)] = r;
+        }
+        rc += CU;
+        rc -= rc >= nc ? nc : 0;
+    }
+    // the last cells one at a time; the right input of cell n_c - 1 is the
+    // first input cell again
+    constexpr int NT = (M + 3) / 4 * 4;
+    for (; i < nc; ++i) {
+        T cur[J][M];
+        const int c = i < nc - 1 ? rc : l0;
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+#pragma unroll
+            for (int l = 0; l < M; ++l) cur[j][l] = ld(c, l, j);
+        double vals[NT];
+#pragma unroll
+        for (int q = 0; q < NT; ++q) vals[q] = 0.0;
+        cell(i, cur, vals);
+#pragma unroll
+        for (int g = 0; g < NT / 4; ++g) {
+            const double r = wave_sum4_rows(vals[4 * g], vals[4 * g + 1], vals[4 * g + 2], vals[4 * g + 3]);
+            const int q = 4 * g + (lane >> 4);
+            if ((lane & 15) == 0 && q < M) rp[wave * N + i * M + q] = r;
+        }
         rc = rc + 1 == nc ? 0 : rc + 1;
     }
     if (MOM) {
@@ -555,6 +552,139 @@ sldg_col_rho(const T* __restrict__ fin, T* __restrict__ fout,
         double acc = 0.0;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; ++w) acc += red[threadIdx.x * (kBlock / 64) + w];
+        rf.mom_part[static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x] = acc;
+    }
+}
+
+// The x2 sweep with its output density formed on the way, by row segments
+// as `sldg_seg` (band blocks: x1 index o, segment q, block kb of 256 threads,
+// kb fastest).  A thread takes J velocity columns that share the x2 shift
+// (one v2, J consecutive v1 nodes: columns k0 + j N4) under one operator,
+// forms the C output cells of its segment in each, and adds W3 W4 f_out over
+// its columns into one value per output node; the wavefront sums those
+// C (l+1) values four at a time (`wave_sum4_rows`), the four wavefronts'
+// sums meet in LDS, and the workgroup writes its slice [q C (l+1),
+// (q C + C)(l+1)) of the partial density of its 256 J columns, the layout
+// of one group per 256 J columns.  The x1 plane is read and written as a
+// buffer (less than 4 GB).
+template <int M, typename T, int C, int J, bool MOM>
+__global__ void __launch_bounds__(kBlock)
+sldg_seg_rho(const T* __restrict__ fin, T* __restrict__ fout,
+             const double* __restrict__ shift, ShiftMap sm, int nc, int64_t inner, int nseg,
+             NodeBasis basis, RhoFuse rf) {
+    constexpr int NV = C * M;
+    static_assert(NV % 4 == 0, "whole groups of four values");
+    __shared__ double red[kBlock / 64][NV + 4];
+    const int nkb = static_cast<int>(inner / (J * kBlock));
+    const int b = static_cast<int>(blockIdx.x);
+    const int kb = b % nkb;
+    const int rest = b / nkb;
+    const int q = rest % nseg;
+    const int o = rest / nseg;
+    const int t = kb * kBlock + static_cast<int>(threadIdx.x);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int v1b = t / rf.n4;                      // v1 nodes v1b J .. v1b J + J - 1
+    const int v2 = t - v1b * rf.n4;
+    const int k0 = v1b * J * rf.n4 + v2;            // first column
+    const double w4 = rf.g4.w[v2 % rf.g4.m] * rf.g4.h;
+    double w3[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) w3[j] = rf.g3.w[(v1b * J + j) % rf.g3.m] * rf.g3.h;
+
+    int s;
+    T A[M][M], B[M][M];
+    sldg_operator<M, T>(basis, shift[shift_offset(sm, o, k0)], nc, s, A, B);
+    const int64_t cs = static_cast<int64_t>(M) * inner;
+    const uint32_t pb = static_cast<uint32_t>(nc * cs * sizeof(T));
+    const __amdgpu_buffer_rsrc_t rin = buffer_of(fin + static_cast<int64_t>(o) * nc * cs, pb);
+    const __amdgpu_buffer_rsrc_t rout = buffer_of(fout + static_cast<int64_t>(o) * nc * cs, pb);
+    const uint32_t kbyte = static_cast<uint32_t>(k0 * sizeof(T));
+    const uint32_t cb = static_cast<uint32_t>(cs * sizeof(T));
+    const uint32_t ib = static_cast<uint32_t>(inner * sizeof(T));
+    const uint32_t jb = static_cast<uint32_t>(rf.n4 * sizeof(T));
+
+    const int i0 = q * C;
+    int c = i0 - s - 1;   // first input cell, reduced into [0, nc)
+    c += c < 0 ? nc : 0;
+    c -= c >= nc ? nc : 0;
+    T u[C + 1][J][M];
+#pragma unroll
+    for (int i = 0; i <= C; ++i) {
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+#pragma unroll
+            for (int l = 0; l < M; ++l)
+                u[i][j][l] = buffer_load<T>(rin, static_cast<uint32_t>(c) * cb + kbyte, l * ib + j * jb);
+        c = c + 1 == nc ? 0 : c + 1;
+    }
+    double vals[NV];
+    // moments of column j: sums of W2 f, W2 |f|, W2 f^2 over its nodes
+    double x_m[J], x_a[J], x_q[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) x_m[j] = x_a[j] = x_q[j] = 0.0;
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        const bool live = i0 + i < nc;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            double val = 0.0;
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                T acc = T(0);
+#pragma unroll
+                for (int l = 0; l < M; ++l) acc = fma(A[m][l], u[i][j][l], acc);
+#pragma unroll
+                for (int l = 0; l < M; ++l) acc = fma(B[m][l], u[i + 1][j][l], acc);
+                if (live)
+                    buffer_store_nt<T>(acc, rout, kbyte,
+                                       static_cast<uint32_t>((i0 + i) * cs * sizeof(T)) + m * ib + j * jb);
+                const double ov = live ? static_cast<double>(acc) : 0.0;
+                val = fma(w3[j], ov, val);
+                if (MOM) {
+                    const double w2 = rf.g2.w[m] * rf.g2.h;
+                    x_m[j] = fma(w2, ov, x_m[j]);
+                    x_a[j] = fma(w2, fabs(ov), x_a[j]);
+                    x_q[j] = fma(w2 * ov, ov, x_q[j]);
+                }
+            }
+            const int v = i * M + m;
+            vals[v] = w4 * val;
+            if (v % 4 == 3) {   // a group of four values is complete: sum it
+                const double r = wave_sum4_rows(vals[v - 3], vals[v - 2], vals[v - 1], vals[v]);
+                if ((lane & 15) == 0) red[wave][v - 3 + (lane >> 4)] = r;
+            }
+        }
+    }
+    if (MOM) {
+        // W = W1 W2 W3 W4: W2 in the column sums, W3 per column, W1 W4 here
+        const double a2 = rf.g4.lo + (static_cast<double>(v2 / rf.g4.m) + rf.g4.xi[v2 % rf.g4.m]) * rf.g4.h;
+        double s_m = 0.0, s_a = 0.0, s_q = 0.0, s_k = 0.0;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int v1 = v1b * J + j;
+            const double a1 = rf.g3.lo + (static_cast<double>(v1 / rf.g3.m) + rf.g3.xi[v1 % rf.g3.m]) * rf.g3.h;
+            s_m = fma(w3[j], x_m[j], s_m);
+            s_a = fma(w3[j], x_a[j], s_a);
+            s_q = fma(w3[j], x_q[j], s_q);
+            s_k = fma(w3[j] * (a1 * a1 + a2 * a2), x_m[j], s_k);
+        }
+        const double f0 = rf.g1.w[o % rf.g1.m] * rf.g1.h * w4;
+        const double r = wave_sum4_rows(f0 * s_m, f0 * s_a, f0 * s_q, f0 * s_k);
+        if ((lane & 15) == 0) red[wave][NV + (lane >> 4)] = r;
+    }
+    __syncthreads();
+    const int nv = min(C, nc - i0) * M;
+    if (static_cast<int>(threadIdx.x) < nv) {
+        double acc = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) acc += red[w][threadIdx.x];
+        rf.part[(static_cast<int64_t>(o) * nkb + kb) * (nc * M) + i0 * M + threadIdx.x] = acc;
+    }
+    if (MOM && threadIdx.x < 4) {
+        double acc = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) acc += red[w][NV + threadIdx.x];
         rf.mom_part[static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x] = acc;
     }
 }
@@ -778,6 +908,8 @@ vp_status launch_sldg_rho_j(const int64_t dims[4], const void* fin, void* fout,
     const size_t lds = sizeof(double) * (kBlock / 64) * (static_cast<size_t>(dims[1]) + 4);
     if (dims[2] % J || (inner / J) % kBlock || lds > 48 * 1024)
         return set_error(VP_ERR_UNSUPPORTED, "fused x2 sweep needs whole workgroups of columns");
+    if (static_cast<uint64_t>(dims[1] * inner) * sizeof(T) >= (uint64_t(1) << 32))
+        return set_error(VP_ERR_UNSUPPORTED, "fused x2 sweep: an x1 plane of 4 GB or more");
     const unsigned grid = blocks_for(outer * inner / J, kBlock);
     if (rf.mom_part)
         sldg_col_rho<M, T, J, true><<<grid, kBlock, lds, st>>>(
@@ -788,11 +920,68 @@ vp_status launch_sldg_rho_j(const int64_t dims[4], const void* fin, void* fout,
     return check_launch("sldg_col_rho");
 }
 
+// Shape of the fused row-segment sweep: cells per segment (0: whole lines)
+// and velocity columns per thread.
+constexpr int kRhoSegJ32 = 2;   // FP32: columns per thread
+constexpr int kRhoSegC32 = 8;   // FP32: cells per segment
+constexpr int rho_seg_cells(int M, bool f32) {
+    return M > 4 ? 0 : (M == 4 ? kSegCells / 2 : (f32 ? kRhoSegC32 : kSegCells));
+}
+constexpr int rho_seg_cols(int M, bool f32) { return f32 && M <= 3 ? kRhoSegJ32 : 1; }
+
+// The fused x2 sweep runs by row segments where its band blocks apply:
+// N3 N4 / J a multiple of 256, x2 rows of at most 16 MB, an x1 plane under
+// 4 GB and degree <= 3; otherwise one thread per whole line (`sldg_col_rho`).
+int rho_seg_stack(vp_dtype dt, int degree, const int64_t dims[4]) {
+    const int64_t inner = dims[2] * dims[3];
+    const size_t es = dtype_size(dt);
+    const bool f32 = dt == VP_F32;
+    const int C = rho_seg_cells(degree + 1, f32);
+    if (C == 0) return 0;
+    if (static_cast<size_t>(inner) * es > (size_t(16) << 20)) return 0;
+    if (static_cast<uint64_t>(dims[1] * inner) * es >= (uint64_t(1) << 32)) return 0;
+    int J = rho_seg_cols(degree + 1, f32);
+    while (J > 1 && (dims[2] % J || (inner / J) % kBlock)) J /= 2;
+    if ((inner / J) % kBlock) return 0;
+    const int nc = static_cast<int>(dims[1] / (degree + 1));
+    const int64_t nblk = dims[0] * ((nc + C - 1) / C) * (inner / (J * kBlock));
+    return nblk < (int64_t(1) << 31) ? J : 0;
+}
+
+template <int M, typename T, int J>
+vp_status launch_sldg_rho_seg(const int64_t dims[4], const void* fin, void* fout,
+                              const double* shift, const ShiftMap& sm, const RhoFuse& rf,
+                              hipStream_t st) {
+    constexpr int C = rho_seg_cells(M, sizeof(T) == 4);
+    if constexpr (C > 0) {
+        const NodeBasis& b = node_basis(M - 1);
+        const int64_t inner = dims[2] * dims[3];
+        const int nc = static_cast<int>(dims[1] / M);
+        const int nseg = (nc + C - 1) / C;
+        const unsigned grid = static_cast<unsigned>(dims[0] * nseg * (inner / (J * kBlock)));
+        if (rf.mom_part)
+            sldg_seg_rho<M, T, C, J, true><<<grid, kBlock, 0, st>>>(
+                static_cast<const T*>(fin), static_cast<T*>(fout), shift, sm, nc, inner, nseg, b, rf);
+        else
+            sldg_seg_rho<M, T, C, J, false><<<grid, kBlock, 0, st>>>(
+                static_cast<const T*>(fin), static_cast<T*>(fout), shift, sm, nc, inner, nseg, b, rf);
+        return check_launch("sldg_seg_rho");
+    }
+    return set_error(VP_ERR_UNSUPPORTED, "fused x2 sweep by segments: degree <= 3");
+}
+
 template <int M, typename T>
 vp_status launch_sldg_rho(const int64_t dims[4], const void* fin, void* fout,
                           const double* shift, const ShiftMap& sm, const RhoFuse& rf,
                           hipStream_t st) {
-    const int J = sldg_rho_stack(sizeof(T) == 8 ? VP_F64 : VP_F32, M - 1, dims);
+    const vp_dtype dt = sizeof(T) == 8 ? VP_F64 : VP_F32;
+    const int js = rho_seg_stack(dt, M - 1, dims);
+    if (js == 1) return launch_sldg_rho_seg<M, T, 1>(dims, fin, fout, shift, sm, rf, st);
+    if constexpr (rho_seg_cols(M, sizeof(T) == 4) >= 2)
+        if (js == 2) return launch_sldg_rho_seg<M, T, 2>(dims, fin, fout, shift, sm, rf, st);
+    if constexpr (rho_seg_cols(M, sizeof(T) == 4) >= 4)
+        if (js == 4) return launch_sldg_rho_seg<M, T, 4>(dims, fin, fout, shift, sm, rf, st);
+    const int J = sldg_rho_stack(dt, M - 1, dims);
     if (J == 4) {
         if constexpr (M <= 3 && sizeof(T) == 4)
             return launch_sldg_rho_j<M, T, 4>(dims, fin, fout, shift, sm, rf, st);
@@ -1025,6 +1214,8 @@ vp_status sldg_advect_impl(int axis, int degree, vp_dtype dt,
 
 int sldg_rho_stack(vp_dtype dt, int degree, const int64_t dims[4]) {
     const int64_t inner = dims[2] * dims[3];
+    const int js = rho_seg_stack(dt, degree, dims);
+    if (js > 0) return js;
     // FP32, degree <= 2: four columns a thread (the FP32 sweep has half the
     // memory time to hide the density exchanges behind); otherwise, or where
     // the grid does not divide, one
@@ -1035,6 +1226,12 @@ int sldg_rho_stack(vp_dtype dt, int degree, const int64_t dims[4]) {
 }
 
 int64_t sldg_rho_workgroups(vp_dtype dt, int degree, const int64_t dims[4]) {
+    const int js = rho_seg_stack(dt, degree, dims);
+    if (js > 0) {
+        const int nc = static_cast<int>(dims[1] / (degree + 1));
+        const int C = rho_seg_cells(degree + 1, dt == VP_F32);
+        return dims[0] * ((nc + C - 1) / C) * (dims[2] * dims[3] / (js * kBlock));
+    }
     const int J = sldg_rho_stack(dt, degree, dims);
     return J > 0 ? dims[0] * dims[2] * dims[3] / (static_cast<int64_t>(kBlock) * J) : 0;
 }

@@ -576,10 +576,15 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                     }
                     // lanes of one segment: the whole wavefront (64-line
                     // tiles) or its halves (32-line tiles, two segments)
-                    const int gl = threadIdx.x & (L - 1);
-                    const double r = L == 64 ? group_reduce_scatter<4, 64>(vals, threadIdx.x & 63)
-                                             : group_reduce_scatter<4, 32>(vals, threadIdx.x & 63);
-                    if (gl < 4) rf.part[static_cast<int64_t>(blockIdx.x) * n + i + gl] = r;
+                    if (L == 64) {
+                        const double r = wave_sum4_rows(vals[0], vals[1], vals[2], vals[3]);
+                        if ((threadIdx.x & 15) == 0)
+                            rf.part[static_cast<int64_t>(blockIdx.x) * n + i + ((threadIdx.x & 63) >> 4)] = r;
+                    } else {
+                        const int gl = threadIdx.x & (L - 1);
+                        const double r = group_reduce_scatter<4, 32>(vals, threadIdx.x & 63);
+                        if (gl < 4) rf.part[static_cast<int64_t>(blockIdx.x) * n + i + gl] = r;
+                    }
                 }
                 c0 = c4;
                 c1 = c5;

@@ -181,8 +181,13 @@ __device__ __forceinline__ double group_reduce_scatter(double* v, int lane) {
         const bool upper = (lane & m) != 0;
 #pragma unroll
         for (int j = 0; j < m; ++j) {
-            const double keep = upper ? v[j + m] : v[j];
-            const double give = upper ? v[j] : v[j + m];
+            double a = v[j], b = v[j + m];
+            // (register operands for the selects: a select of two array
+            // elements would otherwise become one load at a lane-dependent
+            // index, a compare-and-select chain over all V elements)
+            asm("" : "+v"(a), "+v"(b));
+            const double keep = upper ? b : a;
+            const double give = upper ? a : b;
             v[j] = keep + xor_lanes(give, m);
         }
     }
@@ -190,6 +195,93 @@ __device__ __forceinline__ double group_reduce_scatter(double* v, int lane) {
 #pragma unroll
     for (int m = V; m < G; m <<= 1) r += xor_lanes(r, m);
     return r;
+}
+
+// x + y after a half-wave exchange: with H = 32, lanes 0..31 return
+// x(l) + x(l + 32) and lanes 32..63 return y(l - 32) + y(l); with H = 16 the
+// same within each pair of 16-lane rows (even rows: x, odd rows: y).  One
+// v_permlane{32,16}_swap per 32-bit half (gfx950): the swap exchanges the
+// upper half of x with the lower half of y, so no lane has to select.
+template <int H>
+__device__ __forceinline__ double swap_add(double x, double y) {
+    const unsigned xl = static_cast<unsigned>(__double2loint(x));
+    const unsigned xh = static_cast<unsigned>(__double2hiint(x));
+    const unsigned yl = static_cast<unsigned>(__double2loint(y));
+    const unsigned yh = static_cast<unsigned>(__double2hiint(y));
+    static_assert(H == 32 || H == 16, "half-wave or half-row pair exchange");
+    if constexpr (H == 32) {
+        const auto lo = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+        return __hiloint2double(static_cast<int>(hi[0]), static_cast<int>(lo[0])) +
+               __hiloint2double(static_cast<int>(hi[1]), static_cast<int>(lo[1]));
+    } else {
+        const auto lo = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+        return __hiloint2double(static_cast<int>(hi[0]), static_cast<int>(lo[0])) +
+               __hiloint2double(static_cast<int>(hi[1]), static_cast<int>(lo[1]));
+    }
+}
+
+// v from lane (l + n) mod 16 of the same 16-lane row (DPP row rotation).
+template <int n>
+__device__ __forceinline__ double row_ror(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x120 + n, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x120 + n, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sums over the 64 lanes of a wavefront of four values per lane: on return
+// every lane of row r (lanes 16 r .. 16 r + 15) holds the sum of a_r.  Two
+// half exchanges leave each lane one partial sum over four lanes
+// {l, l ^ 16, l ^ 32, l ^ 48}, added across its row by four rotations.
+__device__ __forceinline__ double wave_sum4_rows(double a0, double a1, double a2, double a3) {
+    const double b0 = swap_add<32>(a0, a2);   // lanes < 32: a0, else a2
+    const double b1 = swap_add<32>(a1, a3);   // lanes < 32: a1, else a3
+    double c = swap_add<16>(b0, b1);          // row r: a_r
+    c += row_ror<8>(c);
+    c += row_ror<4>(c);
+    c += row_ror<2>(c);
+    c += row_ror<1>(c);
+    return c;
+}
+
+// Raw buffer access for kernels whose addresses are a uniform base plus a
+// 32-bit per-lane byte offset: the descriptor and the uniform part (soff)
+// live in scalar registers, so a load or store costs no vector address
+// arithmetic.  `bytes` (< 4 GB) bounds the offsets: the hardware returns 0
+// for a load beyond it and drops such a store.  Word 3 of the descriptor:
+// 32-bit data format, the value for gfx9 buffers.
+// The caller's base and size are the same in every lane; the readfirstlane
+// says so to the compiler, which otherwise may keep the descriptor in vector
+// registers and loop over the lanes at every access.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* base, uint32_t bytes) {
+    const uint64_t a = reinterpret_cast<uint64_t>(base);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(a));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(a >> 32));
+    void* const p = reinterpret_cast<void*>((static_cast<uint64_t>(hi) << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(p, 0, __builtin_amdgcn_readfirstlane(bytes), 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(voff),
+                                                                          static_cast<int>(soff), 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(voff),
+                                                                          static_cast<int>(soff), 0));
+}
+// (non-temporal, as `put_out` below: cache policy bit 1)
+template <typename T>
+__device__ __forceinline__ void buffer_store_nt(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                uint32_t soff) {
+    if constexpr (sizeof(T) == 8) {
+        using U = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, v), r, static_cast<int>(voff),
+                                              static_cast<int>(soff), 2);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r,
+                                              static_cast<int>(voff), static_cast<int>(soff), 2);
+    }
 }
 
 // Store of a sweep output.  Every output element is written once and read
