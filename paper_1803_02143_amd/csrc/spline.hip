@@ -31,7 +31,6 @@ namespace vp {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kU = 4;  // rows per wavefront pass of the row shift derivative
 
 template <typename T>
 struct SplineParams {
@@ -721,28 +720,23 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                 if (e0 + u * kBlock < cnt) buf[pos[u]] = v[u];
         }
     }
-    // shift derivative: the lam values of this wavefront's rows (the row
-    // passes below: rows r0 + u kWaves, column blocks of 64) loaded before the
-    // solve, so that they arrive while it runs; tiles with more rows or
-    // longer rows than the registers hold load lam after the solve
-    constexpr int kPfPass = sizeof(T) == 8 ? 2 : 4;   // passes of kU rows
-    constexpr int kPfCol = 2;                         // column blocks
-    const bool pf = MODE == kDshift && nr <= kPfPass * kU * kWaves && n <= kPfCol * 64;
-    T lpf[MODE == kDshift ? kPfPass * kU * kPfCol : 1];
-    if (MODE == kDshift && pf) {
+    // shift derivative: each thread's segment of lam (the solve's mapping:
+    // row t % R, points [b, e)), loaded before the solve so that it arrives
+    // while the solve runs
+    constexpr int SM = SegMax<T>::value;
+    T lseg[MODE == kDshift ? SM : 1];
+    if (MODE == kDshift) {
+        const int r = threadIdx.x % R;
+        const int Q = kBlock / R;
+        const int S = (n + Q - 1) / Q;
+        const int b = min(n, (static_cast<int>(threadIdx.x) / R) * S);
+        const int e = min(n, b + S);
+        if (r < nr) {
+            const T* __restrict__ lr = lam + (row0 + r) * n;
 #pragma unroll
-        for (int p = 0; p < kPfPass; ++p)
-#pragma unroll
-            for (int u = 0; u < kU; ++u)
-#pragma unroll
-                for (int c = 0; c < kPfCol; ++c) {
-                    const int r = wave + (p * kU + u) * kWaves;
-                    const int i = c * 64 + lane;
-                    // (clamped: every load in range, unused values ignored)
-                    const int rr = r < nr ? r : nr - 1;
-                    const int ii = i < n ? i : n - 1;
-                    lpf[(p * kU + u) * kPfCol + c] = lam[(row0 + rr) * n + ii];
-                }
+            for (int t = 0; t < SM; ++t)
+                if (b + t < e) lseg[t] = lr[b + t];
+        }
     }
     if (threadIdx.x < nr) {
         const int r = threadIdx.x;
@@ -881,83 +875,52 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         }
         return;
     }
-    // shift derivative: kU rows per wavefront at a time (rows r0 + u kWaves),
-    // each row's weights and shift in registers, lanes over the columns; the
-    // kU row sums of the wavefront are reduced together (reduce-scatter).
-    // (Few rows per pass keep the registers, and so the occupancy that hides
-    // the lam loads, at the level of the forward sweep.)
-    if (pf) {
+    // shift derivative: each thread runs the sliding window of the forward
+    // evaluation (one LDS read per point) along its own segment and adds
+    // lam_i v_i in FP64; the segments of a row meet in LDS
+    {
+        const int r = threadIdx.x % R;
+        const int Q = kBlock / R;
+        const int S = (n + Q - 1) / Q;
+        const int q = static_cast<int>(threadIdx.x) / R;
+        const int b = min(n, q * S);
+        const int e = min(n, b + S);
+        double acc = 0.0;
+        if (r < nr && b < e) {
+            const T* row = buf + r * ld;
+            const T w0 = wts[4 * r + 0], w1 = wts[4 * r + 1];
+            const T w2 = wts[4 * r + 2], w3 = wts[4 * r + 3];
+            int j = first_tap(b, sh[r], n);
+            T c0 = row[j];
+            j = next_idx(j, n);
+            T c1 = row[j];
+            j = next_idx(j, n);
+            T c2 = row[j];
+            j = next_idx(j, n);
+            T c3 = row[j];
 #pragma unroll
-        for (int p = 0; p < kPfPass; ++p) {
-            const int r0 = wave + p * kU * kWaves;
-            if (r0 >= nr) break;
-            double acc[kU];
-#pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                acc[u] = 0.0;
-                const int r = r0 + u * kWaves;
-                if (r < nr) {
-                    const T* row = buf + r * ld;
-                    const T w0 = wts[4 * r + 0], w1 = wts[4 * r + 1];
-                    const T w2 = wts[4 * r + 2], w3 = wts[4 * r + 3];
-                    const int s = sh[r];
-#pragma unroll
-                    for (int c = 0; c < kPfCol; ++c) {
-                        const int i = c * 64 + lane;
-                        if (i < n) {
-                            const int j0 = first_tap(i, s, n);
-                            const int j1 = next_idx(j0, n), j2 = next_idx(j1, n);
-                            const int j3 = next_idx(j2, n);
-                            const T v = fma(w3, row[j3], fma(w2, row[j2], fma(w1, row[j1], w0 * row[j0])));
-                            acc[u] = fma(static_cast<double>(lpf[(p * kU + u) * kPfCol + c]),
-                                         static_cast<double>(v), acc[u]);
-                        }
-                    }
-                }
-            }
-            const double a = group_reduce_scatter<kU, 64>(acc, lane);
-            if (lane < kU && r0 + lane * kWaves < nr) g[row0 + r0 + lane * kWaves] = a;
-        }
-        return;
-    }
-    for (int r0 = wave; r0 < nr; r0 += kWaves * kU) {
-        double acc[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) acc[u] = 0.0;
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int r = r0 + u * kWaves;
-            if (r < nr) {
-                const T* row = buf + r * ld;
-                const T* __restrict__ lrow = lam + (row0 + r) * n;
-                const T w0 = wts[4 * r + 0], w1 = wts[4 * r + 1];
-                const T w2 = wts[4 * r + 2], w3 = wts[4 * r + 3];
-                const int s = sh[r];
-                // the first two column blocks unrolled (their loads issued
-                // together across the kU rows), the rest of a long row after
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const int i = c * 64 + lane;
-                    if (i < n) {
-                        const int j0 = first_tap(i, s, n);
-                        const int j1 = next_idx(j0, n), j2 = next_idx(j1, n);
-                        const int j3 = next_idx(j2, n);
-                        const T v = fma(w3, row[j3], fma(w2, row[j2], fma(w1, row[j1], w0 * row[j0])));
-                        acc[u] = fma(static_cast<double>(lrow[i]), static_cast<double>(v), acc[u]);
-                    }
-                }
-                for (int i = 128 + lane; i < n; i += 64) {
-                    const int j0 = first_tap(i, s, n);
-                    const int j1 = next_idx(j0, n), j2 = next_idx(j1, n);
-                    const int j3 = next_idx(j2, n);
-                    const T v = fma(w3, row[j3], fma(w2, row[j2], fma(w1, row[j1], w0 * row[j0])));
-                    acc[u] = fma(static_cast<double>(lrow[i]), static_cast<double>(v), acc[u]);
+            for (int t = 0; t < SM; ++t) {
+                if (b + t < e) {
+                    const T v = fma(w3, c3, fma(w2, c2, fma(w1, c1, w0 * c0)));
+                    acc = fma(static_cast<double>(lseg[t]), static_cast<double>(v), acc);
+                    c0 = c1;
+                    c1 = c2;
+                    c2 = c3;
+                    j = next_idx(j, n);
+                    c3 = row[j];
                 }
             }
         }
-        // lane u (< kU) receives the sum of row r0 + u kWaves
-        const double a = group_reduce_scatter<kU, 64>(acc, lane);
-        if (lane < kU && r0 + lane * kWaves < nr) g[row0 + r0 + lane * kWaves] = a;
+        // (the tile is free: every thread is past its last read of it)
+        __syncthreads();
+        double* red = reinterpret_cast<double*>(smem);   // [Q][R]
+        red[q * R + r] = acc;
+        __syncthreads();
+        if (static_cast<int>(threadIdx.x) < nr) {
+            double t = 0.0;
+            for (int qq = 0; qq < Q; ++qq) t += red[qq * R + threadIdx.x];
+            g[row0 + threadIdx.x] = t;
+        }
     }
 }
 
@@ -1045,8 +1008,11 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
     if (static_cast<size_t>(R) * (n + 1) * sizeof(T) > kTileBytes)
         return set_error(VP_ERR_UNSUPPORTED,
                          "spline_advect: line of %d points too long for the LDS tile", n);
-    const size_t lds = static_cast<size_t>(R) * (n + 1) * sizeof(T) +
-                       static_cast<size_t>(R) * (4 * sizeof(T) + sizeof(int));
+    // (the shift derivative adds its segment sums in the tile afterwards:
+    // kBlock doubles)
+    const size_t lds = std::max(static_cast<size_t>(R) * (n + 1) * sizeof(T) +
+                                    static_cast<size_t>(R) * (4 * sizeof(T) + sizeof(int)),
+                                MODE == kDshift ? kBlock * sizeof(double) : size_t(0));
     const int64_t grid64 = (outer + R - 1) / R;
     if (grid64 >= (int64_t(1) << 31))
         return set_error(VP_ERR_UNSUPPORTED, "spline_advect: grid too large");
