@@ -22,6 +22,7 @@
 // thread per line runs the two recursions; all threads load, evaluate and
 // store element-parallel with contiguous global accesses.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <type_traits>
 
@@ -411,8 +412,8 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
             // (one row's 16 adjacent lines) makes the outputs of lines gi,
             // gi+16, .. (NC = L/16 of them) at the R = n/16 rows of one
             // segment, adding their weighted values per row in registers.
-            // R <= kR: a 64-line tile holds at most 96 / 192 points a line in
-            // FP64 / FP32, a 32-line FP64 tile 192.  (Both shapes compiled
+            // R <= kR: a 64-line tile holds at most 128 / 192 points a line
+            // in FP64 / FP32, a 32-line FP64 tile 192.  (Both shapes compiled
             // with constant NC and kR.)
             auto line_groups = [&](auto nc_c, auto kr_c) {
                 constexpr int NC = decltype(nc_c)::value;
@@ -517,7 +518,7 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
             };
             if (L == 64)
                 line_groups(std::integral_constant<int, 4>{},
-                            std::integral_constant<int, sizeof(T) == 8 ? 6 : 12>{});
+                            std::integral_constant<int, sizeof(T) == 8 ? 8 : 12>{});
             else
                 line_groups(std::integral_constant<int, 2>{}, std::integral_constant<int, 12>{});
             return;
@@ -939,10 +940,17 @@ SplineParams<T> make_params(int n) {
 
 constexpr size_t kTileBytes = 48 * 1024;
 
+// The fused x2 sweeps' column tiles may take 64 KiB (64-line FP64 tiles up
+// to 128 points a line, evaluated by line groups: two workgroups a compute
+// unit); the other sweeps keep 48 KiB (at 128^4 the plain FP64 sweeps ran
+// 3-11 % slower with the larger tiles), within which every segment also fits
+// the transposed and shift-derivative sweeps' register arrays (SegMax).
+constexpr size_t kFwdTileBytes = 64 * 1024;
+
 // lines per column tile: a power of two up to 64 within the LDS budget
-int tile_lines(int n, size_t esize) {
+int tile_lines(int n, size_t esize, size_t budget = kTileBytes) {
     int L = 64;
-    while (L > 1 && static_cast<size_t>(n) * L * esize > kTileBytes) L /= 2;
+    while (L > 1 && static_cast<size_t>(n) * L * esize > budget) L /= 2;
     return L;
 }
 
@@ -960,7 +968,9 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
     const T* lm = static_cast<const T*>(lam);
     if (axis < 3) {
         // tiles run over the flattened line index
-        const int L = tile_lines(n, sizeof(T));
+        constexpr bool RHO = MODE == kFwdRho || MODE == kFwdRhoMom;
+        const size_t budget = RHO ? kFwdTileBytes : kTileBytes;
+        const int L = tile_lines(n, sizeof(T), budget);
         size_t lds = static_cast<size_t>(n) * L * sizeof(T);
         // tiles with the density evaluated by line groups: the tile is
         // reused for the row sums (n rows of 17) and the moment partials
@@ -969,13 +979,25 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
             lds = std::max(lds, (static_cast<size_t>(n) * 17 + 4 * kBlock + 64) * sizeof(double));
         if ((MODE == kFwdRho || MODE == kFwdRhoMom) &&
             (axis != 1 || (L != 64 && L != 32) || inner % L || n % (kBlock / L) ||
-             inner >= (int64_t(1) << 31) ||
-             (L == 64 && sizeof(T) == 8 && (n % 16 || n > 96))))
+             inner >= (int64_t(1) << 31)))
             return set_error(VP_ERR_UNSUPPORTED,
                              "fused x2 sweep needs 32- or 64-line tiles of equal segments");
-        if (lds > kTileBytes)
+        if (lds > budget)
             return set_error(VP_ERR_UNSUPPORTED,
                              "spline_advect: line of %d points too long for the LDS tile", n);
+        if (lds > kTileBytes) {
+            static std::atomic<bool> attr_set{false};
+            if (!attr_set.load(std::memory_order_relaxed)) {
+                // dynamic LDS beyond the default (one setting covers the axes)
+                const void* fns[3] = {reinterpret_cast<const void*>(&spline_col<T, 0, MODE>),
+                                      reinterpret_cast<const void*>(&spline_col<T, 1, MODE>),
+                                      reinterpret_cast<const void*>(&spline_col<T, 2, MODE>)};
+                for (const void* fn : fns)
+                    VP_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   static_cast<int>(kFwdTileBytes)));
+                attr_set.store(true, std::memory_order_relaxed);
+            }
+        }
         const int64_t nlines = outer * inner;
         const int64_t grid64 = (nlines + L - 1) / L;
         if (grid64 >= (int64_t(1) << 31))
@@ -1056,12 +1078,10 @@ vp_status spline_advect_rho_impl(vp_dtype dt, const int64_t dims[4], const void*
 int spline_rho_group(vp_dtype dt, const int64_t dims[4]) {
     // the lanes of a segment must run the same evaluation steps: tiles of 64
     // lines (one segment per wavefront) or 32 (two), segments of equal length
-    const int L = tile_lines(static_cast<int>(dims[1]), dtype_size(dt));
+    const int L = tile_lines(static_cast<int>(dims[1]), dtype_size(dt), kFwdTileBytes);
     if (L != 64 && L != 32) return 0;
     if ((dims[2] * dims[3]) % L || dims[1] % (kBlock / L)) return 0;
     if (dims[2] * dims[3] >= (int64_t(1) << 31)) return 0;   // 32-bit velocity index
-    // 16 row segments of the FP64 evaluation by line groups
-    if (L == 64 && dt == VP_F64 && dims[1] % 16) return 0;
     return L;
 }
 
