@@ -365,10 +365,12 @@ sldg_seg(const T* __restrict__ fin, T* __restrict__ fout,
     }
 }
 
-// The x2 sweep with its output density formed on the way (forward only).
-// The x2 shift depends on v2 only, so a thread takes J velocity columns
-// that share it: the same v2 and J consecutive v1 nodes (columns k0 + j N4),
-// with one operator for all of them.  Output cells are produced in order,
+// The x2 sweep with its output density formed on the way (forward only), by
+// whole lines: the form for the shapes the row-segment form below does not
+// take (degree above 3, x2 rows over 16 MB, x1 planes of 4 GB or more),
+// launched with J = 1.  The x2 shift depends on v2 only, so a thread may
+// take J velocity columns that share it: the same v2 and J consecutive v1
+// nodes (columns k0 + j N4), with one operator for all of them.  Output cells are produced in order,
 // every lane of a wavefront on the same cell: output i is fed by input
 // cells (l0 + i, l0 + i + 1) mod n_c with l0 = n_c - 1 - s, which lanes load
 // from their own (shift-dependent) rows.  A lane first adds W3 W4 f_out
@@ -981,16 +983,8 @@ vp_status launch_sldg_rho(const int64_t dims[4], const void* fin, void* fout,
         if (js == 2) return launch_sldg_rho_seg<M, T, 2>(dims, fin, fout, shift, sm, rf, st);
     if constexpr (rho_seg_cols(M, sizeof(T) == 4) >= 4)
         if (js == 4) return launch_sldg_rho_seg<M, T, 4>(dims, fin, fout, shift, sm, rf, st);
-    const int J = sldg_rho_stack(dt, M - 1, dims);
-    if (J == 4) {
-        if constexpr (M <= 3 && sizeof(T) == 4)
-            return launch_sldg_rho_j<M, T, 4>(dims, fin, fout, shift, sm, rf, st);
-    }
-    if (J == 2) {
-        if constexpr (M <= 4)
-            return launch_sldg_rho_j<M, T, 2>(dims, fin, fout, shift, sm, rf, st);
-    }
-    if (J == 1) return launch_sldg_rho_j<M, T, 1>(dims, fin, fout, shift, sm, rf, st);
+    if (sldg_rho_stack(dt, M - 1, dims) == 1)
+        return launch_sldg_rho_j<M, T, 1>(dims, fin, fout, shift, sm, rf, st);
     return set_error(VP_ERR_UNSUPPORTED, "fused x2 sweep needs whole workgroups of columns");
 }
 
@@ -1216,13 +1210,8 @@ int sldg_rho_stack(vp_dtype dt, int degree, const int64_t dims[4]) {
     const int64_t inner = dims[2] * dims[3];
     const int js = rho_seg_stack(dt, degree, dims);
     if (js > 0) return js;
-    // FP32, degree <= 2: four columns a thread (the FP32 sweep has half the
-    // memory time to hide the density exchanges behind); otherwise, or where
-    // the grid does not divide, one
-    int J = degree <= 2 && dt == VP_F32 ? 4 : 1;
-    while (J > 1 && (dims[2] % J || (inner / J) % kBlock)) J /= 2;
-    if (inner % kBlock && J == 1) return 0;
-    return J;
+    // whole lines (`sldg_col_rho`): one column a thread
+    return inner % kBlock ? 0 : 1;
 }
 
 int64_t sldg_rho_workgroups(vp_dtype dt, int degree, const int64_t dims[4]) {
