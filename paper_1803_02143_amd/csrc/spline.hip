@@ -214,10 +214,12 @@ enum { kFwd = 0, kAdj = 1, kDshift = 2, kFwdRho = 3, kFwdRhoMom = 4 };
 
 // Longest segment a thread owns: tiles hold at most kTileBytes, so a
 // segment has at most kTileBytes / (kBlock * sizeof(T)) points.
-// Tiles whose fused density evaluation runs by line groups: 64 lines, or 32
-// lines in FP64 (rows of at most 192 points), lines of a multiple of 16.
+// Tiles whose fused density evaluation runs by line groups: FP64 tiles of 64
+// or 32 lines (rows of at most 128 / 192 points), lines of a multiple of 16.
+// (FP32 tiles evaluate by lines with wavefront sums: 160 against 168 us at
+// 96^4, where the FP64 line groups win, 277 against 283 us.)
 __host__ __device__ constexpr bool line_group_tile(int L, int n, int esize) {
-    return (L == 64 || (L == 32 && esize == 8)) && n % 16 == 0;
+    return esize == 8 && (L == 64 || L == 32) && n % 16 == 0;
 }
 
 template <typename T>

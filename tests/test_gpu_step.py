@@ -335,8 +335,8 @@ def test_run_with_every_step_formed_is_the_plain_step():
     ("spline", "f64", (2, 128, 8, 16)),
     # 32-line FP64 tiles by line groups (two lines a thread, up to 12 rows)
     ("spline", "f64", (2, 192, 8, 16)),
-    # FP32 64-line tiles up to the longest line the tile holds; lines that
-    # are no multiple of 16 points keep the per-line evaluation
+    # FP32 64-line tiles (per-line evaluation) up to the longest line the
+    # tile holds
     ("spline", "f32", (6, 48, 8, 16)), ("spline", "f32", (4, 192, 8, 16)),
     ("spline", "f32", (4, 40, 8, 16)), ("spline", "f32", (4, 200, 8, 16)),
 ])
