@@ -8,6 +8,15 @@
 // and stays fixed during B, which leaves the density unchanged.  Every sweep
 // reads one buffer and writes the other; six sweeps per step return the
 // result to the caller's buffer.  No host synchronisation inside a step.
+//
+// The diagnostics of a state whose density and moments came with its closing
+// x2 sweep (W from the Poisson solve of that density, the moment sums) run
+// on a second stream of the state, with buffers of their own, while the next
+// step's sweeps run on the caller's stream: the closing sweep writes its
+// partial sums to those buffers, an event hands them to the second stream,
+// and the next closing sweep waits for the diagnostics that read them.  The
+// caller's stream waits for the last diagnostics before the call returns, so
+// every result is ordered after the call on that stream.
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -34,6 +43,13 @@ struct vp_state {
     double* partial;  // 4 * n1 * n2
     double *gs1, *gs2, *rho_bar;  // adjoint: shift gradients and transposed density
     void* pws;        // Poisson workspace
+    // diagnostics on the second stream: partial densities of the closing x2
+    // sweep, field arrays, Poisson workspace; events that order the streams
+    hipStream_t side;
+    hipEvent_t side_ready, side_done;
+    double* rho_part_d;
+    double *rho_d, *e1_d, *e2_d;
+    void* pws_d;
     bool timing;
     std::vector<hipEvent_t> ev[VP_TIMER_COUNT];  // start/stop pairs
     std::vector<hipEvent_t> free_events;
@@ -99,13 +115,14 @@ vp_status sweep(vp_state* st, int axis, const void* in, void* out,
 // it, the sweep also writes the partial densities of its output (and the
 // field then sums them instead of reading the state again).
 vp_status sweep_x2_rho(vp_state* st, const void* in, void* out, const double* shift,
-                       hipStream_t s, bool& fused, bool moments = false) {
+                       hipStream_t s, bool& fused, bool moments = false,
+                       double* part = nullptr) {
     fused = st->rho_groups > 0;
     if (!fused) return sweep(st, 1, in, out, shift, s);
     int64_t stride[4];
     step_strides(st, 1, stride);
     RhoFuse rf{};
-    rf.part = st->rho_part;
+    rf.part = part ? part : st->rho_part;
     rf.mom_part = moments ? st->mom_part : nullptr;
     rf.g1 = axis_grid(st->degree, st->dims[0], st->lo[0], st->len[0]);
     rf.g2 = axis_grid(st->degree, st->dims[1], st->lo[1], st->len[1]);
@@ -121,18 +138,19 @@ vp_status sweep_x2_rho(vp_state* st, const void* in, void* out, const double* sh
     return rc;
 }
 
-// W (and the moments) of the state just written by a fused x2 sweep, from
-// its partial sums.
+// W (and the moments) of the state just written by a fused closing x2
+// sweep, from its partial sums (rho_part_d, mom_part), with the second
+// stream's field arrays; s is the second stream.
 vp_status diagnostics_fused(vp_state* st, double* W, double* mom, hipStream_t s) {
     mark(st, VP_TIMER_DIAG, s);
     vp_status rc = VP_OK;
     if (mom) rc = moments_from_parts_impl(st->mom_part, st->mom_parts, st->mom_chunk, mom, s);
     if (rc == VP_OK && W)
-        rc = rho_from_parts_impl(st->rho_part, st->dims[0], st->rho_groups, st->dims[1],
-                                 st->rho, s);
+        rc = rho_from_parts_impl(st->rho_part_d, st->dims[0], st->rho_groups, st->dims[1],
+                                 st->rho_d, s);
     if (rc == VP_OK && W)
         rc = poisson_impl(st->degree, st->dims[0], st->dims[1], st->len[0], st->len[1],
-                          st->rho, st->e1, st->e2, W, st->pws, s);
+                          st->rho_d, st->e1_d, st->e2_d, W, st->pws_d, s);
     mark(st, VP_TIMER_DIAG, s);
     return rc;
 }
@@ -242,9 +260,12 @@ extern "C" vp_status vp_create(vp_state** out, int method, int degree, vp_dtype 
     if (static_cast<size_t>(dims[0] * groups * dims[1]) * sizeof(double) > fbytes / 16) groups = 0;
     const size_t npart = static_cast<size_t>(dims[0] * groups * dims[1]);
     const int64_t nwg = groups > 0 ? rho_fuse_workgroups(method, deg, dt, dims) : 0;
-    const size_t ndbl = static_cast<size_t>(nx) * (5 + 4 + 3) +
-                        3 * static_cast<size_t>(dims[2] + dims[3]) + pws / sizeof(double) + 64 +
-                        npart + 4 * static_cast<size_t>(nwg) + moments_chunk_doubles() + 32;
+    // (with the second stream's partial densities, field arrays and Poisson
+    // workspace)
+    const size_t ndbl = static_cast<size_t>(nx) * (5 + 4 + 3 + 3) +
+                        3 * static_cast<size_t>(dims[2] + dims[3]) +
+                        2 * (pws / sizeof(double) + 64) + 2 * npart +
+                        4 * static_cast<size_t>(nwg) + moments_chunk_doubles() + 32;
     void* mem = nullptr;
     hipError_t e = hipMalloc(&mem, ndbl * sizeof(double));
     if (e != hipSuccess) {
@@ -277,6 +298,14 @@ extern "C" vp_status vp_create(vp_state** out, int method, int degree, vp_dtype 
     p += 4 * nwg;
     st->mom_chunk = p;
     p += moments_chunk_doubles();
+    st->rho_part_d = p;
+    p += npart;
+    st->rho_d = p; p += nx;
+    st->e1_d = p; p += nx;
+    st->e2_d = p; p += nx;
+    p = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(p) + 255) & ~uintptr_t(255));
+    st->pws_d = p;
+    p += pws / sizeof(double) + 32;
     p = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(p) + 255) & ~uintptr_t(255));
     st->pws = p;
     // velocity node coordinates, used for the x-sweep shifts
@@ -295,6 +324,20 @@ extern "C" vp_status vp_create(vp_state** out, int method, int degree, vp_dtype 
         delete st;
         return set_error(VP_ERR_HIP, "hipMemcpy failed: %s", hipGetErrorString(e));
     }
+    // the second stream (default priority, not synchronising with the null
+    // stream) and its two events
+    st->side = nullptr;
+    st->side_ready = st->side_done = nullptr;
+    e = hipStreamCreateWithFlags(&st->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&st->side_ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&st->side_done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        if (st->side_ready) (void)hipEventDestroy(st->side_ready);
+        if (st->side) (void)hipStreamDestroy(st->side);
+        (void)hipFree(mem);
+        delete st;
+        return set_error(VP_ERR_HIP, "stream or event creation failed: %s", hipGetErrorString(e));
+    }
     st->timing = false;
     *out = st;
     return VP_OK;
@@ -309,6 +352,9 @@ extern "C" void vp_destroy(vp_state* st) {
     for (auto& v : st->ev)
         for (hipEvent_t e : v) (void)hipEventDestroy(e);
     for (hipEvent_t e : st->free_events) (void)hipEventDestroy(e);
+    (void)hipEventDestroy(st->side_ready);
+    (void)hipEventDestroy(st->side_done);
+    (void)hipStreamDestroy(st->side);
     (void)hipFree(st->buf);
     if (cur != st->device) (void)hipSetDevice(cur);
     delete st;
@@ -341,6 +387,17 @@ vp_status strang_run(vp_state* st, void* f, void* f_tmp, int nsteps, double tau,
     }
     const bool diag = W_trace || moments;
     if (diag && (rc = diagnostics(st, f, W_trace, moments, s)) != VP_OK) return rc;
+    // diagnostics in flight on the second stream: the caller's stream waits
+    // for them before returning, whatever the outcome
+    bool side_used = false;
+    struct Join {
+        vp_state* st;
+        hipStream_t s;
+        bool& used;
+        ~Join() {
+            if (used) (void)hipStreamWaitEvent(s, st->side_done, 0);
+        }
+    } join{st, s, side_used};
     for (int seg = 0; seg < nsteps / every; ++seg) {
         bool fused = false;
         if ((rc = sweep(st, 0, f, f_tmp, st->sig_x1, s)) != VP_OK) return rc;
@@ -363,18 +420,31 @@ vp_status strang_run(vp_state* st, void* f, void* f_tmp, int nsteps, double tau,
                 return rc;
             if (!last)
                 rc = sweep_x2_rho(st, f_tmp, f, st->sig_x2f, s, fused);
-            else if (diag)
-                // the state of the diagnostics: its density and moments
-                // come with the closing sweep
-                rc = sweep_x2_rho(st, f_tmp, f, st->sig_x2, s, fused, moments != nullptr);
-            else
+            else if (diag) {
+                // the state of the diagnostics: its density and moments come
+                // with the closing sweep, into the second stream's partial
+                // sums (once the previous diagnostics have read them)
+                if (side_used) VP_HIP_TRY(hipStreamWaitEvent(s, st->side_done, 0));
+                rc = sweep_x2_rho(st, f_tmp, f, st->sig_x2, s, fused, moments != nullptr,
+                                  st->rho_part_d);
+            } else
                 rc = sweep(st, 1, f_tmp, f, st->sig_x2, s);
             if (rc != VP_OK) return rc;
         }
         if (diag) {
             double* Wd = W_trace ? W_trace + seg + 1 : nullptr;
             double* md = moments ? moments + 4 * (seg + 1) : nullptr;
-            rc = fused ? diagnostics_fused(st, Wd, md, s) : diagnostics(st, f, Wd, md, s);
+            if (fused) {
+                VP_HIP_TRY(hipEventRecord(st->side_ready, s));
+                VP_HIP_TRY(hipStreamWaitEvent(st->side, st->side_ready, 0));
+                side_used = true;
+                rc = diagnostics_fused(st, Wd, md, st->side);
+                const hipError_t e = hipEventRecord(st->side_done, st->side);
+                if (rc == VP_OK && e != hipSuccess)
+                    rc = set_error(VP_ERR_HIP, "hipEventRecord failed: %s", hipGetErrorString(e));
+            } else {
+                rc = diagnostics(st, f, Wd, md, s);
+            }
             if (rc != VP_OK) return rc;
         }
     }
