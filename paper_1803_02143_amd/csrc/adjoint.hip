@@ -61,8 +61,8 @@ density_adjoint_kernel(const double* __restrict__ rho_bar, T* __restrict__ lam, 
             for (int u = 0; u < kU; ++u) {
                 if (e + u * 64 < total) {
                     const double v = rb * w[u];
-                    blk[e + u * 64] = ACC ? static_cast<T>(static_cast<double>(old[u]) + v)
-                                          : static_cast<T>(v);
+                    put_out(&blk[e + u * 64], ACC ? static_cast<T>(static_cast<double>(old[u]) + v)
+                                                  : static_cast<T>(v));
                 }
             }
         }

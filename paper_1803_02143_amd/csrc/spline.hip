@@ -450,12 +450,9 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                     for (int r = 0; r < kR; ++r) {
                         if (r < R) {
                             const T ov = fma(a3, c3, fma(a2, c2, fma(a1, c1, a0 * c0)));
-                            // (FP32: a group's 64-byte row pieces are half lines;
-                            // they stay cached to merge before write-back)
-                            if constexpr (sizeof(T) == 8)
-                                put_out(&dl[static_cast<int64_t>(r0 + r) * inner], ov);
-                            else
-                                dl[static_cast<int64_t>(r0 + r) * inner] = ov;
+                            // (a group's row piece: 16 FP64 values, a whole
+                            // 128-byte line)
+                            put_out(&dl[static_cast<int64_t>(r0 + r) * inner], ov);
                             const double od = static_cast<double>(ov);
                             rs[r] = fma(wkl, od, rs[r]);
                             if (MOM) {
