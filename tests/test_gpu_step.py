@@ -301,6 +301,50 @@ def test_merged_run_parity(method, dt):
     st.close()
 
 
+def test_diagnostics_are_ordered_on_the_callers_stream():
+    # the diagnostics of the fused states run on the state's second stream;
+    # on return, work queued on the caller's stream must see all of them:
+    # copies queued right after the call, on a stream of the caller's own,
+    # equal the results of the same run on the default stream
+    vp = require_gpu()
+    w = workload("landau_8")
+    dims = (12, 12, 16, 16)   # fused x2 sweeps for both methods (SLDG degree 1)
+    for method in (vp.METHOD_SLDG, vp.METHOD_SPLINE):
+        st = vp.VPState(method, 1, torch.float64, dims, w.lo, w.length)
+        f0 = torch.empty(dims, dtype=torch.float64, device="cuda")
+        vp.vp_init(vp.IC_LANDAU, w.eps, w.k, 0.0, 1 if method == vp.METHOD_SLDG else -1, f0,
+                   w.lo, w.length)
+        torch.cuda.synchronize()
+        nsteps = 6
+        # reference: default stream, synchronised
+        a = f0.clone()
+        tmp = torch.empty_like(a)
+        Wa = torch.empty(nsteps + 1, dtype=torch.float64, device="cuda")
+        ma = torch.empty(4 * (nsteps + 1), dtype=torch.float64, device="cuda")
+        announce(f"diagnostics stream order, method {method}")
+        st.timing_enable(True)
+        st.step(a, tmp, nsteps, w.dt, Wa, ma)
+        torch.cuda.synchronize()
+        timers = st.timing_read()
+        st.timing_enable(False)
+        assert timers["sweep_x2_rho"][1] == 2 * nsteps, timers
+        # the caller's own stream; the copies are queued behind the call
+        s1 = torch.cuda.Stream()
+        b = f0.clone()
+        Wb = torch.full((nsteps + 1,), float("nan"), dtype=torch.float64, device="cuda")
+        mb = torch.full((4 * (nsteps + 1),), float("nan"), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s1):
+            st.step(b, tmp, nsteps, w.dt, Wb, mb, stream=s1)
+            Wc = Wb.clone()
+            mc = mb.clone()
+        s1.synchronize()
+        assert torch.equal(a, b)
+        assert torch.equal(Wa, Wc), (Wa, Wc)
+        assert torch.equal(ma, mc), (ma, mc)
+        st.close()
+
+
 def test_run_with_every_step_formed_is_the_plain_step():
     vp = require_gpu()
     w = workload("landau_8")
