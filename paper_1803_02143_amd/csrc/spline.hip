@@ -536,14 +536,11 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         j = next_idx(j, n);
         T c3 = buf[j * L + l];
         int i = b;
-        // density weight of this line's velocity column
-        double wk = 0.0;
-        if (RHO) {
-            const int k32 = static_cast<int>(kl);   // velocity index (< 2^31 here)
-            const int v1 = k32 / rf.n4;
-            const int v2 = k32 - v1 * rf.n4;
-            wk = rf.g3.w[v1 % rf.g3.m] * rf.g3.h * (rf.g4.w[v2 % rf.g4.m] * rf.g4.h);
-        }
+        // density weight of the velocity columns: the spline's velocity
+        // nodes are one per cell with equal weights (checked on the host),
+        // so the weight multiplies the wavefront's sums instead of every
+        // value
+        const double wk = RHO ? rf.g3.w[0] * rf.g3.h * (rf.g4.w[0] * rf.g4.h) : 0.0;
         if (FWD) {
             for (; i + 4 <= e; i += 4) {
                 const int j4 = next_idx(j, n), j5 = next_idx(j4, n);
@@ -560,17 +557,15 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                 put_out(&dst[static_cast<int64_t>(i + 3) * inner], o3);
                 if (RHO) {
                     // the wavefront's 64 lines share i: sums over them
-                    double vals[4] = {wk * static_cast<double>(o0), wk * static_cast<double>(o1),
-                                      wk * static_cast<double>(o2), wk * static_cast<double>(o3)};
+                    double vals[4] = {static_cast<double>(o0), static_cast<double>(o1),
+                                      static_cast<double>(o2), static_cast<double>(o3)};
                     if (MOM) {
-                        const double w2 = rf.g2.h;
-                        const double ov[4] = {static_cast<double>(o0), static_cast<double>(o1),
-                                              static_cast<double>(o2), static_cast<double>(o3)};
+                        // (the x2 weight, equal for all nodes, is applied at the end)
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            s_m = fma(w2, ov[q], s_m);
-                            s_a = fma(w2, fabs(ov[q]), s_a);
-                            s_q = fma(w2 * ov[q], ov[q], s_q);
+                            s_m += vals[q];
+                            s_a += fabs(vals[q]);
+                            s_q = fma(vals[q], vals[q], s_q);
                         }
                     }
                     // lanes of one segment: the whole wavefront (64-line
@@ -578,11 +573,11 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                     if (L == 64) {
                         const double r = wave_sum4_rows(vals[0], vals[1], vals[2], vals[3]);
                         if ((threadIdx.x & 15) == 0)
-                            rf.part[static_cast<int64_t>(blockIdx.x) * n + i + ((threadIdx.x & 63) >> 4)] = r;
+                            rf.part[static_cast<int64_t>(blockIdx.x) * n + i + ((threadIdx.x & 63) >> 4)] = wk * r;
                     } else {
                         const int gl = threadIdx.x & (L - 1);
                         const double r = group_reduce_scatter<4, 32>(vals, threadIdx.x & 63);
-                        if (gl < 4) rf.part[static_cast<int64_t>(blockIdx.x) * n + i + gl] = r;
+                        if (gl < 4) rf.part[static_cast<int64_t>(blockIdx.x) * n + i + gl] = wk * r;
                     }
                 }
                 c0 = c4;
@@ -597,17 +592,16 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                 const T o = fma(w3, c3, fma(w2, c2, fma(w1, c1, w0 * c0)));
                 put_out(&dst[static_cast<int64_t>(i) * inner], o);
                 if (RHO) {
-                    double vals[1] = {wk * static_cast<double>(o)};
+                    double vals[1] = {static_cast<double>(o)};
                     if (MOM) {
-                        const double ov = static_cast<double>(o);
-                        s_m = fma(rf.g2.h, ov, s_m);
-                        s_a = fma(rf.g2.h, fabs(ov), s_a);
-                        s_q = fma(rf.g2.h * ov, ov, s_q);
+                        s_m += vals[0];
+                        s_a += fabs(vals[0]);
+                        s_q = fma(vals[0], vals[0], s_q);
                     }
                     const double r = L == 64 ? group_reduce_scatter<1, 64>(vals, threadIdx.x & 63)
                                              : group_reduce_scatter<1, 32>(vals, threadIdx.x & 63);
                     if ((threadIdx.x & (L - 1)) == 0)
-                        rf.part[static_cast<int64_t>(blockIdx.x) * n + i] = r;
+                        rf.part[static_cast<int64_t>(blockIdx.x) * n + i] = wk * r;
                 }
                 c0 = c1;
                 c1 = c2;
@@ -648,16 +642,13 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         const double a1 = rf.g3.lo + (static_cast<double>(v1) + rf.g3.xi[0]) * rf.g3.h;
         const double a2 = rf.g4.lo + (static_cast<double>(v2) + rf.g4.xi[0]) * rf.g4.h;
         const double wv = rf.g3.h * rf.g4.h;
-        const double f0 = rf.g1.h * wv;
-        double q[4] = {f0 * s_m, f0 * s_a, f0 * s_q, f0 * (a1 * a1 + a2 * a2) * s_m};
+        const double f0 = rf.g1.h * wv * rf.g2.h;   // the weights (one node per cell)
         const int lane = threadIdx.x & 63;
         const int wave = threadIdx.x >> 6;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) q[t] += __shfl_xor(q[t], off, 64);
-            if (lane == 0) mred[t * (kBlock / 64) + wave] = q[t];
-        }
+        // one wavefront sum of the four: row t of the wavefront holds sum t
+        const double r = wave_sum4_rows(f0 * s_m, f0 * s_a, f0 * s_q,
+                                        f0 * (a1 * a1 + a2 * a2) * s_m);
+        if ((lane & 15) == 0) mred[(lane >> 4) * (kBlock / 64) + wave] = r;
         __syncthreads();
         if (threadIdx.x < 4) {
             double t = 0.0;
@@ -1060,6 +1051,10 @@ vp_status spline_advect_rho_impl(vp_dtype dt, const int64_t dims[4], const void*
                                  void* f_out, const double* shift,
                                  const int64_t shift_stride[4], const RhoFuse& rf,
                                  hipStream_t st) {
+    // (point grids: one node per cell on every axis, so the quadrature
+    // weights of a velocity column and of an x2 node do not vary)
+    if (rf.g1.m != 1 || rf.g2.m != 1 || rf.g3.m != 1 || rf.g4.m != 1)
+        return set_error(VP_ERR_UNSUPPORTED, "fused spline x2 sweep: point grids only");
     const ShiftMap sm = make_shift_map(1, dims, shift_stride);
     if (dt == VP_F64)
         return rf.mom_part
