@@ -423,9 +423,13 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                 const int gi = threadIdx.x & 15;
                 const int R = n / 16;
                 const int r0 = (static_cast<int>(threadIdx.x) >> 4) * R;
+                // (point grids: the velocity-column weight is the same for
+                // every line and the x2 weight for every node, so both
+                // multiply the sums at the end)
+                const double wk = pwk[0];
                 const double w2x = rf.g2.h;
                 T* __restrict__ tile = fout + o * n * inner + (kl - l);
-                double qm[4] = {0.0, 0.0, 0.0, 0.0};
+                double qm[4] = {0.0, 0.0, 0.0, 0.0};   // f, |f|, f^2, |v|^2 f
                 double rs[kR];
 #pragma unroll
                 for (int t = 0; t < kR; ++t) rs[t] = 0.0;
@@ -434,9 +438,8 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                     const int ln = gi + 16 * c;
                     const T a0 = pw[4 * ln], a1 = pw[4 * ln + 1];
                     const T a2 = pw[4 * ln + 2], a3 = pw[4 * ln + 3];
-                    const double wkl = pwk[ln];
-                    const double wm = wkl * w2x;
                     const double vv = MOM ? pvv[ln] : 0.0;
+                    double sl = 0.0;   // this line's sum (the |v|^2 moment)
                     T* __restrict__ dl = tile + ln;
                     int j = first_tap(r0, ps[ln], n);
                     T c0 = buf[j * L + ln];
@@ -454,12 +457,11 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                             // 128-byte line)
                             put_out(&dl[static_cast<int64_t>(r0 + r) * inner], ov);
                             const double od = static_cast<double>(ov);
-                            rs[r] = fma(wkl, od, rs[r]);
+                            rs[r] += od;
                             if (MOM) {
-                                qm[0] = fma(wm, od, qm[0]);
-                                qm[1] = fma(wm, fabs(od), qm[1]);
-                                qm[2] = fma(wm * od, od, qm[2]);
-                                qm[3] = fma(wm * vv, od, qm[3]);
+                                sl += od;
+                                qm[1] += fabs(od);
+                                qm[2] = fma(od, od, qm[2]);
                             }
                             c0 = c1;
                             c1 = c2;
@@ -468,7 +470,15 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                             c3 = buf[j * L + ln];
                         }
                     }
+                    if (MOM) {
+                        qm[0] += sl;
+                        qm[3] = fma(vv, sl, qm[3]);
+                    }
                 }
+#pragma unroll
+                for (int t = 0; t < kR; ++t) rs[t] *= wk;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) qm[q] *= wk * w2x;
                 // Sums through the (now free) tile, no cross-lane exchanges:
                 // thread (gi, p) puts its R row partials at
                 // red_rows[(p R + r) 17 + gi] (rows padded to 17 against bank
