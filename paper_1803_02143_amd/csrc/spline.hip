@@ -219,7 +219,7 @@ enum { kFwd = 0, kAdj = 1, kDshift = 2, kFwdRho = 3, kFwdRhoMom = 4 };
 // (FP32 tiles evaluate by lines with wavefront sums: 160 against 168 us at
 // 96^4, where the FP64 line groups win, 277 against 283 us.)
 __host__ __device__ constexpr bool line_group_tile(int L, int n, int esize) {
-    return esize == 8 && (L == 64 || L == 32) && n % 16 == 0;
+    return esize == 8 && n % 16 == 0 && ((L == 64 && n <= 128) || (L == 32 && n <= 192));
 }
 
 template <typename T>
