@@ -24,7 +24,6 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
-#include <type_traits>
 
 #include "field.hpp"
 
@@ -214,14 +213,6 @@ enum { kFwd = 0, kAdj = 1, kDshift = 2, kFwdRho = 3, kFwdRhoMom = 4 };
 
 // Longest segment a thread owns: tiles hold at most kTileBytes, so a
 // segment has at most kTileBytes / (kBlock * sizeof(T)) points.
-// Tiles whose fused density evaluation runs by line groups: FP64 tiles of 64
-// or 32 lines (rows of at most 128 / 192 points), lines of a multiple of 16.
-// (FP32 tiles evaluate by lines with wavefront sums: 160 against 168 us at
-// 96^4, where the FP64 line groups win, 277 against 283 us.)
-__host__ __device__ constexpr bool line_group_tile(int L, int n, int esize) {
-    return esize == 8 && n % 16 == 0 && ((L == 64 && n <= 128) || (L == 32 && n <= 192));
-}
-
 template <typename T>
 struct SegMax {
     static constexpr int value = 48 * 1024 / (256 * static_cast<int>(sizeof(T)));
@@ -302,12 +293,6 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     constexpr bool FWD = MODE == kFwd || RHO;
     __shared__ double mred[MOM ? 4 * (kBlock / 64) : 1];
     double s_m = 0.0, s_a = 0.0, s_q = 0.0;   // W2 f, W2 |f|, W2 f^2 of this line
-    // line-group tiles with the density: each line's weights, shift,
-    // density weight and |v|^2, for the evaluation by line groups
-    constexpr bool LG = RHO;
-    __shared__ T pw[LG ? 4 * 64 : 1];
-    __shared__ int ps[LG ? 64 : 1];
-    __shared__ double pwk[LG ? 64 : 1], pvv[LG ? 64 : 1];
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[MODE == kDshift ? kBlock : 1];
     const int n = sp.n;
@@ -383,21 +368,6 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         w2 = wq[2];
         w3 = wq[3];
     }
-    if (LG && line_group_tile(L, n, sizeof(T)) && static_cast<int>(threadIdx.x) < L) {
-        // (the first segment's thread of every line; all 64 lines are whole)
-        pw[4 * l] = w0;
-        pw[4 * l + 1] = w1;
-        pw[4 * l + 2] = w2;
-        pw[4 * l + 3] = w3;
-        ps[l] = s;
-        const int k32 = static_cast<int>(kl);   // velocity index (< 2^31 here)
-        const int v1 = k32 / rf.n4;
-        const int v2 = k32 - v1 * rf.n4;
-        pwk[l] = rf.g3.w[v1 % rf.g3.m] * rf.g3.h * (rf.g4.w[v2 % rf.g4.m] * rf.g4.h);
-        const double a1 = rf.g3.lo + (static_cast<double>(v1) + rf.g3.xi[0]) * rf.g3.h;
-        const double a2 = rf.g4.lo + (static_cast<double>(v2) + rf.g4.xi[0]) * rf.g4.h;
-        pvv[l] = a1 * a1 + a2 * a2;
-    }
     __syncthreads();
     if (MODE == kAdj) transposed_taps<T>(buf + l, L, b, e, s, n, w0, w1, w2, w3, active);
     spline_solve_segment<T>(buf + l, L, b, e, active, sp);
@@ -407,131 +377,6 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
             for (int i = b; i < e; ++i) put_out(&dst[static_cast<int64_t>(i) * inner], buf[i * L + l]);
         }
         return;
-    }
-    if constexpr (LG) {
-        if (line_group_tile(L, n, sizeof(T))) {
-            // Evaluation by (line group, row segment): a group of 16 lanes
-            // (one row's 16 adjacent lines) makes the outputs of lines gi,
-            // gi+16, .. (NC = L/16 of them) at the R = n/16 rows of one
-            // segment, adding their weighted values per row in registers.
-            // R <= kR: a 64-line tile holds at most 128 / 192 points a line
-            // in FP64 / FP32, a 32-line FP64 tile 192.  (Both shapes compiled
-            // with constant NC and kR.)
-            auto line_groups = [&](auto nc_c, auto kr_c) {
-                constexpr int NC = decltype(nc_c)::value;
-                constexpr int kR = decltype(kr_c)::value;
-                const int gi = threadIdx.x & 15;
-                const int R = n / 16;
-                const int r0 = (static_cast<int>(threadIdx.x) >> 4) * R;
-                // (point grids: the velocity-column weight is the same for
-                // every line and the x2 weight for every node, so both
-                // multiply the sums at the end)
-                const double wk = pwk[0];
-                const double w2x = rf.g2.h;
-                T* __restrict__ tile = fout + o * n * inner + (kl - l);
-                double qm[4] = {0.0, 0.0, 0.0, 0.0};   // f, |f|, f^2, |v|^2 f
-                double rs[kR];
-#pragma unroll
-                for (int t = 0; t < kR; ++t) rs[t] = 0.0;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    const int ln = gi + 16 * c;
-                    const T a0 = pw[4 * ln], a1 = pw[4 * ln + 1];
-                    const T a2 = pw[4 * ln + 2], a3 = pw[4 * ln + 3];
-                    const double vv = MOM ? pvv[ln] : 0.0;
-                    double sl = 0.0;   // this line's sum (the |v|^2 moment)
-                    T* __restrict__ dl = tile + ln;
-                    int j = first_tap(r0, ps[ln], n);
-                    T c0 = buf[j * L + ln];
-                    j = next_idx(j, n);
-                    T c1 = buf[j * L + ln];
-                    j = next_idx(j, n);
-                    T c2 = buf[j * L + ln];
-                    j = next_idx(j, n);
-                    T c3 = buf[j * L + ln];
-#pragma unroll
-                    for (int r = 0; r < kR; ++r) {
-                        if (r < R) {
-                            const T ov = fma(a3, c3, fma(a2, c2, fma(a1, c1, a0 * c0)));
-                            // (a group's row piece: 16 FP64 values, a whole
-                            // 128-byte line)
-                            put_out(&dl[static_cast<int64_t>(r0 + r) * inner], ov);
-                            const double od = static_cast<double>(ov);
-                            rs[r] += od;
-                            if (MOM) {
-                                sl += od;
-                                qm[1] += fabs(od);
-                                qm[2] = fma(od, od, qm[2]);
-                            }
-                            c0 = c1;
-                            c1 = c2;
-                            c2 = c3;
-                            j = next_idx(j, n);
-                            c3 = buf[j * L + ln];
-                        }
-                    }
-                    if (MOM) {
-                        qm[0] += sl;
-                        qm[3] = fma(vv, sl, qm[3]);
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < kR; ++t) rs[t] *= wk;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) qm[q] *= wk * w2x;
-                // Sums through the (now free) tile, no cross-lane exchanges:
-                // thread (gi, p) puts its R row partials at
-                // red_rows[(p R + r) 17 + gi] (rows padded to 17 against bank
-                // conflicts) and, with the moments, its four moment partials at
-                // red_mom[q 256 + t].  After a barrier thread i < n adds the 16
-                // line groups of row i in order; the last wavefront (idle there:
-                // n <= 192) adds the moment partials in 64 strided chunks of 16,
-                // and after another barrier four threads add the chunks.
-                __syncthreads();
-                double* red_rows = reinterpret_cast<double*>(smem);
-                double* red_mom = red_rows + n * 17;      // [4][256]
-                double* red_chunk = red_mom + 4 * kBlock;  // [4][16]
-#pragma unroll
-                for (int r = 0; r < kR; ++r)
-                    if (r < R) red_rows[(r0 + r) * 17 + gi] = rs[r];
-                if (MOM) {
-                    const double w1x = rf.g1.h;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) red_mom[q * kBlock + threadIdx.x] = w1x * qm[q];
-                }
-                __syncthreads();
-                if (static_cast<int>(threadIdx.x) < n) {
-                    const double* q = red_rows + threadIdx.x * 17;
-                    double t = 0.0;
-#pragma unroll
-                    for (int g = 0; g < 16; ++g) t += q[g];
-                    rf.part[static_cast<int64_t>(blockIdx.x) * n + threadIdx.x] = t;
-                }
-                if (MOM) {
-                    if (threadIdx.x >= kBlock - 64) {
-                        const int k = threadIdx.x - (kBlock - 64);
-                        const double* q = red_mom + (k >> 4) * kBlock + (k & 15);
-                        double t = 0.0;
-#pragma unroll
-                        for (int u = 0; u < kBlock / 16; ++u) t += q[16 * u];
-                        red_chunk[k] = t;
-                    }
-                    __syncthreads();
-                    if (threadIdx.x < 4) {
-                        double t = 0.0;
-#pragma unroll
-                        for (int c = 0; c < 16; ++c) t += red_chunk[threadIdx.x * 16 + c];
-                        rf.mom_part[static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x] = t;
-                    }
-                }
-            };
-            if (L == 64)
-                line_groups(std::integral_constant<int, 4>{},
-                            std::integral_constant<int, sizeof(T) == 8 ? 8 : 12>{});
-            else
-                line_groups(std::integral_constant<int, 2>{}, std::integral_constant<int, 12>{});
-            return;
-        }
     }
     double acc = 0.0;
     if (active) {
@@ -941,10 +786,12 @@ SplineParams<T> make_params(int n) {
 constexpr size_t kTileBytes = 48 * 1024;
 
 // The fused x2 sweeps' column tiles may take 64 KiB (64-line FP64 tiles up
-// to 128 points a line, evaluated by line groups: two workgroups a compute
-// unit); the other sweeps keep 48 KiB (at 128^4 the plain FP64 sweeps ran
-// 3-11 % slower with the larger tiles), within which every segment also fits
-// the transposed and shift-derivative sweeps' register arrays (SegMax).
+// to 128 points a line, so that a wavefront's lanes are one segment of 64
+// lines and its sums are whole-wavefront sums; two workgroups a compute
+// unit: 1023 against 1072 us at 128^4); the other sweeps keep 48 KiB (at
+// 128^4 the plain FP64 sweeps ran 3-11 % slower with the larger tiles),
+// within which every segment also fits the transposed and shift-derivative
+// sweeps' register arrays (SegMax).
 constexpr size_t kFwdTileBytes = 64 * 1024;
 
 // lines per column tile: a power of two up to 64 within the LDS budget
@@ -972,11 +819,6 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
         const size_t budget = RHO ? kFwdTileBytes : kTileBytes;
         const int L = tile_lines(n, sizeof(T), budget);
         size_t lds = static_cast<size_t>(n) * L * sizeof(T);
-        // tiles with the density evaluated by line groups: the tile is
-        // reused for the row sums (n rows of 17) and the moment partials
-        // (4 x 256 + 64)
-        if ((MODE == kFwdRho || MODE == kFwdRhoMom) && line_group_tile(L, n, sizeof(T)))
-            lds = std::max(lds, (static_cast<size_t>(n) * 17 + 4 * kBlock + 64) * sizeof(double));
         if ((MODE == kFwdRho || MODE == kFwdRhoMom) &&
             (axis != 1 || (L != 64 && L != 32) || inner % L || n % (kBlock / L) ||
              inner >= (int64_t(1) << 31)))

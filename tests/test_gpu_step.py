@@ -368,19 +368,14 @@ def test_run_with_every_step_formed_is_the_plain_step():
     ("sldg", "f64", (12, 10, 16, 16)), ("sldg", "f32", (12, 10, 16, 16)),
     # (N2 a multiple of 256/L, 4 for 64-line tiles)
     ("spline", "f64", (10, 16, 16, 16)), ("spline", "f32", (12, 12, 16, 16)),
-    # per-line evaluation: 64-line FP64 tiles of lines that are no multiple
-    # of 16 points, and 32-line tiles (two segments per wavefront)
+    # 64-line FP64 tiles (one segment a wavefront) up to 128 points a line
+    # (64 KiB tiles), and 32-line tiles (two segments per wavefront)
     ("spline", "f64", (6, 104, 16, 16)), ("spline", "f64", (2, 136, 8, 16)),
     ("spline", "f32", (2, 264, 8, 16)),
-    # 64-line tiles, evaluated by line groups over n/16-row segments (FP64
-    # up to 128 points a line, 64 KiB tiles)
     ("spline", "f64", (6, 16, 16, 16)), ("spline", "f64", (4, 96, 8, 16)),
     ("spline", "f64", (4, 48, 8, 16)), ("spline", "f64", (4, 112, 8, 16)),
-    ("spline", "f64", (2, 128, 8, 16)),
-    # 32-line FP64 tiles by line groups (two lines a thread, up to 12 rows)
-    ("spline", "f64", (2, 192, 8, 16)),
-    # FP32 64-line tiles (per-line evaluation) up to the longest line the
-    # tile holds
+    ("spline", "f64", (2, 128, 8, 16)), ("spline", "f64", (2, 192, 8, 16)),
+    # FP32 64-line tiles up to the longest line the tile holds
     ("spline", "f32", (6, 48, 8, 16)), ("spline", "f32", (4, 192, 8, 16)),
     ("spline", "f32", (4, 40, 8, 16)), ("spline", "f32", (4, 200, 8, 16)),
 ])
