@@ -36,14 +36,16 @@ struct RhoFuse {
     int n4;              // N4 (v2 nodes), to split the column index
 };
 // Velocity columns per group of the fused spline x2 sweep (0: no fused
-// path for this grid); the SLDG one uses groups of 256 columns when N3 N4 is
-// a multiple of 256.
+// path for this grid); the SLDG one uses groups of 256 J columns when
+// N3 N4 / J is a multiple of 256.
 int spline_rho_group(vp_dtype dt, const int64_t dims[4]);
 // Velocity columns per thread of the fused SLDG x2 sweep (J columns that
-// share the x2 shift: one v2, J consecutive v1 nodes), so a workgroup holds
-// 256 J columns; 0 when N3 N4 is no multiple of 256 (no fused path).
+// share the x2 shift: one v2, J consecutive v1 nodes; J = 2 in FP32 by row
+// segments, else 1), so a workgroup holds 256 J columns; 0 when N3 N4 is no
+// multiple of 256 (no fused path).
 int sldg_rho_stack(vp_dtype dt, int degree, const int64_t dims[4]);
-// Workgroups of the fused SLDG x2 sweep (one moment partial each).
+// Workgroups of the fused SLDG x2 sweep that sums the moments (one moment
+// partial each).
 int64_t sldg_rho_workgroups(vp_dtype dt, int degree, const int64_t dims[4]);
 vp_status sldg_advect_rho_impl(int degree, vp_dtype dt, const int64_t dims[4],
                                const void* f_in, void* f_out, const double* shift,
