@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <type_traits>
 
 #include "field.hpp"
 
@@ -240,10 +241,9 @@ __device__ __forceinline__ void spline_dweights(double sigma, int n, int& s, T w
 // Transposed evaluation on a segment, in place, called by every thread:
 // mu_k = w3 lam_{k+s-1} + w2 lam_{k+s} + w1 lam_{k+s+1} + w0 lam_{k+s+2}
 // for k in [b, e) (the gather form of the four-tap scatter).
-template <typename T>
+template <typename T, int SM = SegMax<T>::value>
 __device__ __forceinline__ void transposed_taps(T* p, int stride, int b, int e, int s, int n,
                                                 T w0, T w1, T w2, T w3, bool active) {
-    constexpr int SM = SegMax<T>::value;
     T mu[SM];
     if (active) {
         int j = b + s - 1;
@@ -283,8 +283,10 @@ __device__ __forceinline__ void transposed_taps(T* p, int stride, int b, int e, 
 //   kFwd:    fout = E(alpha) C^{-1} fin
 //   kAdj:    fout = C^{-1} E(alpha)^T fin            (fin = adjoint of the output)
 //   kDshift: g[line] = <lam, E'(alpha) C^{-1} fin>    (per-line shift derivative)
-template <typename T, int AXIS, int MODE>
-__global__ void __launch_bounds__(kBlock)
+// LS bounds the thread's segment: the FP64 loads in flight, the shift
+// derivative's lam and the transposed taps take that many registers.
+template <typename T, int AXIS, int MODE, int LS = SegMax<T>::value>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LS == 16 ? 5 : 1)))
 spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ lam,
            double* __restrict__ g, const double* __restrict__ shift, ShiftMap sm,
            int64_t nlines, int64_t inner, int L, SplineParams<T> sp, RhoFuse rf) {
@@ -316,10 +318,10 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     const T* __restrict__ src = fin + lbase;
     if (active) {
         if constexpr (sizeof(T) == 8) {
-            // FP64: the whole 24-point segment's loads in flight at once
-            // (the tile size already limits the occupancy), clamped indices,
-            // only the LDS stores guarded
-            constexpr int kSeg = 24;
+            // FP64: the whole segment's loads in flight at once (the tile
+            // size already limits the occupancy), clamped indices, only the
+            // LDS stores guarded
+            constexpr int kSeg = LS;
             for (int i0 = b; i0 < e; i0 += kSeg) {
                 T v[kSeg];
 #pragma unroll
@@ -346,7 +348,7 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     }
     // shift derivative: the thread's segment of lam, in flight during the
     // solve (clamped indices, no branches between the loads)
-    constexpr int SM = SegMax<T>::value;
+    constexpr int SM = LS;
     T lv[MODE == kDshift ? SM : 1];
     if (MODE == kDshift && active) {
         const T* __restrict__ lm = lam + lbase;
@@ -369,7 +371,7 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         w3 = wq[3];
     }
     __syncthreads();
-    if (MODE == kAdj) transposed_taps<T>(buf + l, L, b, e, s, n, w0, w1, w2, w3, active);
+    if (MODE == kAdj) transposed_taps<T, LS>(buf + l, L, b, e, s, n, w0, w1, w2, w3, active);
     spline_solve_segment<T>(buf + l, L, b, e, active, sp);
     if (MODE == kAdj) {
         if (active) {
@@ -517,9 +519,12 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
 // Lines along the contiguous axis.  The R rows of a tile are one contiguous
 // range of memory: loads and stores run over it flat (consecutive lanes,
 // consecutive addresses, no idle lanes at row ends); the solve gives thread t
-// row r = t % R and segment q = t / R.  Modes as for spline_col.
-template <typename T, int MODE>
-__global__ void __launch_bounds__(kBlock)
+// row r = t % R and segment q = t / R.  Modes as for spline_col; LS (shift
+// derivative and transposed sweep) bounds the thread's segment, so that the
+// registers that hold its lam through the solve, or its transposed taps,
+// match the segment and not the longest one.
+template <typename T, int MODE, int LS>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LS == 16 ? 5 : 1)))
 spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ lam,
            double* __restrict__ g, const double* __restrict__ shift, ShiftMap sm,
            int64_t nrows, int R, SplineParams<T> sp) {
@@ -569,7 +574,7 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     // shift derivative: each thread's segment of lam (the solve's mapping:
     // row t % R, points [b, e)), loaded before the solve so that it arrives
     // while the solve runs
-    constexpr int SM = SegMax<T>::value;
+    constexpr int SM = LS;
     T lseg[MODE == kDshift ? SM : 1];
     if (MODE == kDshift) {
         const int r = threadIdx.x % R;
@@ -608,7 +613,7 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         const int e = min(n, b + S);
         const bool active = r < nr && b < e;
         if (MODE == kAdj)
-            transposed_taps<T>(buf + r * ld, 1, b, e, active ? sh[r] : 0, n,
+            transposed_taps<T, LS>(buf + r * ld, 1, b, e, active ? sh[r] : 0, n,
                                active ? wts[4 * r] : T(0), active ? wts[4 * r + 1] : T(0),
                                active ? wts[4 * r + 2] : T(0), active ? wts[4 * r + 3] : T(0),
                                active);
@@ -848,16 +853,34 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
         if constexpr (MODE == kFwdRho || MODE == kFwdRhoMom) {
             spline_col<T, 1, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
         } else {
-            switch (axis) {
-                case 0:
-                    spline_col<T, 0, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
-                    break;
-                case 1:
-                    spline_col<T, 1, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
-                    break;
-                default:
-                    spline_col<T, 2, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
-                    break;
+            auto go = [&](auto ls) {
+                constexpr int LS = decltype(ls)::value;
+                switch (axis) {
+                    case 0:
+                        spline_col<T, 0, MODE, LS><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
+                        break;
+                    case 1:
+                        spline_col<T, 1, MODE, LS><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
+                        break;
+                    default:
+                        spline_col<T, 2, MODE, LS><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
+                        break;
+                }
+            };
+            // segment of ceil(n / (kBlock / L)) points: 16 or 24 registers
+            // where it fits (FP32 forward loads go in batches of 12 and take
+            // none of them)
+            const int Q = kBlock / L;
+            const int S = (n + Q - 1) / Q;
+            if constexpr (sizeof(T) == 4 && MODE == kFwd) {
+                go(std::integral_constant<int, SegMax<T>::value>{});
+            } else {
+                if (S <= 16)
+                    go(std::integral_constant<int, 16>{});
+                else if (S <= 24 || sizeof(T) == 8)
+                    go(std::integral_constant<int, 24>{});
+                else
+                    go(std::integral_constant<int, SegMax<T>::value>{});
             }
         }
         return check_launch("spline_col");
@@ -880,8 +903,23 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
     const int64_t grid64 = (outer + R - 1) / R;
     if (grid64 >= (int64_t(1) << 31))
         return set_error(VP_ERR_UNSUPPORTED, "spline_advect: grid too large");
-    spline_row<T, MODE><<<static_cast<unsigned>(grid64), kBlock, lds, st>>>(in, out, lm, g, shift,
-                                                                          sm, outer, R, sp);
+    const unsigned grid = static_cast<unsigned>(grid64);
+    if constexpr (MODE == kDshift || MODE == kAdj) {
+        // segment of ceil(n / (kBlock / R)) points; 16 or 24 registers where
+        // it fits (the FP64 shift derivative at 96 points, 12 a segment: 4
+        // against 6 wavefronts a SIMD with the 24-point bound)
+        const int Q = kBlock / R;
+        const int S = (n + Q - 1) / Q;
+        if (S <= 16)
+            spline_row<T, MODE, 16><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, outer, R, sp);
+        else if (S <= 24 || sizeof(T) == 8)
+            spline_row<T, MODE, 24><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, outer, R, sp);
+        else
+            spline_row<T, MODE, SegMax<T>::value><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm,
+                                                                            outer, R, sp);
+    } else {
+        spline_row<T, MODE, 1><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, outer, R, sp);
+    }
     return check_launch("spline_row");
     }
 }

@@ -256,3 +256,26 @@ def test_differentiated_landau_full_size():
     assert err_g <= max(3.0 * err_J, 3e-6), (err_g, err_J)
     assert err_fd <= max(3.0 * err_J, 3e-6), (err_fd, err_J)
     assert err_m <= 1e-5, err_m
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("n", [80, 96, 150])
+@pytest.mark.parametrize("axis", [1, 3])
+def test_spline_adjoint_segment_lengths(dt, n, axis):
+    # lines whose per-thread segments span the three register bounds of the
+    # transposed sweep and the shift derivative (16, 24 and 48 points),
+    # along a strided axis and the contiguous one, ragged last tiles
+    vp = require_gpu()
+    dims = (3, n, 5, 7) if axis == 1 else (3, 4, 5, n)
+    u = random_field(dims, seed=21)
+    lam = random_field(dims, seed=22)
+    ud, ld = to_dev(u, dt), to_dev(lam, dt)
+    ur, lr = to_host(ud), to_host(ld)
+    sig = _line_shifts(dims, axis, seed=23, n_cells=n, scale=4.0)
+    out = torch.empty_like(ld)
+    g = torch.empty(int(np.prod(dims)) // n, dtype=torch.float64, device="cuda")
+    announce(f"spline adjoint/dshift {dt} axis={axis} n={n}")
+    vp.spline_advect_adjoint(axis, ld, out, to_dev(sig))
+    vp.spline_advect_dshift(axis, ud, ld, to_dev(sig), g)
+    assert_close(to_host(out), adjoint.spline_sweep_adjoint(lr, axis, sig), dt, "adjoint")
+    assert_close(to_host(g), adjoint.spline_sweep_dshift(ur, lr, axis, sig).reshape(-1), dt, "dshift")
