@@ -316,11 +316,15 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     const int e = min(n, b + S);
     const bool active = l < nl && b < e;
     const T* __restrict__ src = fin + lbase;
+    // the line's shift first: loads complete in order, so the wait for it
+    // then covers none of the line's or lam's loads
+    const double sigma = active ? shift[shift_offset(sm, o, kl)] : 0.0;
     if (active) {
         if constexpr (sizeof(T) == 8) {
             // FP64: the whole segment's loads in flight at once (the tile
-            // size already limits the occupancy), clamped indices, only the
-            // LDS stores guarded
+            // size already limits the occupancy), indices clamped to the
+            // segment's last point, whose slot the clamped loads store again
+            // (no branch for the compiler to sink a load into)
             constexpr int kSeg = LS;
             for (int i0 = b; i0 < e; i0 += kSeg) {
                 T v[kSeg];
@@ -328,8 +332,7 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                 for (int u = 0; u < kSeg; ++u)
                     v[u] = src[static_cast<int64_t>(min(i0 + u, e - 1)) * inner];
 #pragma unroll
-                for (int u = 0; u < kSeg; ++u)
-                    if (i0 + u < e) buf[(i0 + u) * L + l] = v[u];
+                for (int u = 0; u < kSeg; ++u) buf[min(i0 + u, e - 1) * L + l] = v[u];
             }
         } else {
             // FP32: batches of 12 loads (registers, not the tile, limit the
@@ -360,7 +363,6 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     T w0 = T(0), w1 = T(0), w2 = T(0), w3 = T(0);
     if (active) {
         T wq[4];
-        const double sigma = shift[shift_offset(sm, o, kl)];
         if (MODE == kDshift)
             spline_dweights<T>(sigma, n, s, wq);
         else
@@ -522,9 +524,12 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
 // row r = t % R and segment q = t / R.  Modes as for spline_col; LS (shift
 // derivative and transposed sweep) bounds the thread's segment, so that the
 // registers that hold its lam through the solve, or its transposed taps,
-// match the segment and not the longest one.
-template <typename T, int MODE, int LS>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LS == 16 ? 5 : 1)))
+// match the segment and not the longest one.  RW > 0 (shift derivative):
+// the evaluation goes by rows instead, wavefront w taking rows w, w + 4, ...
+// (RW of them) and lane l points l, l + 64, ... (CW of them), so that lam
+// arrives by whole-row loads.
+template <typename T, int MODE, int LS, int RW = 0, int CW = 0>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LS == 16 || RW > 0 ? 6 : 1)))
 spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ lam,
            double* __restrict__ g, const double* __restrict__ shift, ShiftMap sm,
            int64_t nrows, int R, SplineParams<T> sp) {
@@ -540,9 +545,14 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     constexpr int kWaves = kBlock / 64;
+    // the row's shift first: loads complete in order, so the wait for it
+    // then covers none of the tile's or lam's loads
+    const double sigma = static_cast<int>(threadIdx.x) < nr
+                             ? shift[shift_offset(sm, row0 + threadIdx.x, 0)] : 0.0;
     // the tile's rows are contiguous in memory: flat element e = r*n + i,
     // (r, i) advanced by kBlock elements per round; kUR loads in flight with
-    // clamped indices, only the LDS stores guarded
+    // indices clamped to the last element, whose slot the clamped lanes
+    // store again (no branch for the compiler to sink a load into)
     const int cnt = nr * n;
     const int dr = kBlock / n;
     const int di = kBlock - dr * n;
@@ -566,17 +576,32 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                     ++r;
                 }
             }
+            const int lastpos = (nr - 1) * ld + n - 1;
 #pragma unroll
-            for (int u = 0; u < kUR; ++u)
-                if (e0 + u * kBlock < cnt) buf[pos[u]] = v[u];
+            for (int u = 0; u < kUR; ++u) buf[e0 + u * kBlock < cnt ? pos[u] : lastpos] = v[u];
         }
     }
     // shift derivative: each thread's segment of lam (the solve's mapping:
     // row t % R, points [b, e)), loaded before the solve so that it arrives
     // while the solve runs
     constexpr int SM = LS;
-    T lseg[MODE == kDshift ? SM : 1];
-    if (MODE == kDshift) {
+    T lseg[MODE == kDshift && RW == 0 ? SM : 1];
+    T lrow[RW > 0 ? RW * CW : 1];
+    if constexpr (MODE == kDshift && RW > 0) {
+        // the wavefront's rows of lam, read along the rows (clamped
+        // indices; the out-of-tile values are never used)
+        const T* __restrict__ lr = lam + row0 * n;
+        const int last = cnt - 1;
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+#pragma unroll
+            for (int m = 0; m < CW; ++m) {
+                const int r = wave + kWaves * k;
+                const int i = lane + 64 * m;
+                lrow[k * CW + m] = lr[r < nr && i < n ? r * n + i : last];
+            }
+        }
+    } else if (MODE == kDshift) {
         const int r = threadIdx.x % R;
         const int Q = kBlock / R;
         const int S = (n + Q - 1) / Q;
@@ -593,7 +618,6 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         const int r = threadIdx.x;
         int s;
         T wq[4];
-        const double sigma = shift[shift_offset(sm, row0 + r, 0)];
         if (MODE == kDshift)
             spline_dweights<T>(sigma, n, s, wq);
         else
@@ -723,6 +747,40 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                 i -= n;
                 ++r;
             }
+        }
+        return;
+    }
+    if constexpr (RW > 0) {
+        // shift derivative by rows: per-lane sums of lam_i v_i in FP64 for
+        // four rows at a time, whose wavefront sums one wave_sum4_rows gives
+        // (lane 16k holds row k's)
+#pragma unroll
+        for (int k0 = 0; k0 < RW; k0 += 4) {
+            double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int r = wave + kWaves * (k0 + kk);
+                if (k0 + kk < RW && r < nr) {
+                    const T* row = buf + r * ld;
+                    const T w0 = wts[4 * r + 0], w1 = wts[4 * r + 1];
+                    const T w2 = wts[4 * r + 2], w3 = wts[4 * r + 3];
+                    const int s = sh[r];
+#pragma unroll
+                    for (int m = 0; m < CW; ++m) {
+                        const int i = lane + 64 * m;
+                        if (i < n) {
+                            const int j0 = first_tap(i, s, n);
+                            const int j1 = next_idx(j0, n), j2 = next_idx(j1, n), j3 = next_idx(j2, n);
+                            const T v = fma(w3, row[j3], fma(w2, row[j2], fma(w1, row[j1], w0 * row[j0])));
+                            a[kk] = fma(static_cast<double>(lrow[(k0 + kk) * CW + m]),
+                                        static_cast<double>(v), a[kk]);
+                        }
+                    }
+                }
+            }
+            const double t = wave_sum4_rows(a[0], a[1], a[2], a[3]);
+            const int r = wave + kWaves * (k0 + (lane >> 4));
+            if ((lane & 15) == 0 && r < nr) g[row0 + r] = t;
         }
         return;
     }
@@ -910,6 +968,34 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
         // against 6 wavefronts a SIMD with the 24-point bound)
         const int Q = kBlock / R;
         const int S = (n + Q - 1) / Q;
+        if constexpr (MODE == kDshift) {
+            // by rows where the wavefront's share of lam fits 16-24 FP64 or
+            // 16-40 FP32 registers: rows per wavefront and 64-point chunks
+            // per row (rows of up to 64, 128, 192 and 320 points)
+            const int rw = R / (kBlock / 64), cw = (n + 63) / 64;
+            auto rows = [&](auto rwc, auto cwc) {
+                spline_row<T, MODE, 1, decltype(rwc)::value, decltype(cwc)::value>
+                    <<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, outer, R, sp);
+                return check_launch("spline_row");
+            };
+            using I16 = std::integral_constant<int, 16>;
+            using I8 = std::integral_constant<int, 8>;
+            using I4 = std::integral_constant<int, 4>;
+            using I5 = std::integral_constant<int, 5>;
+            using I3 = std::integral_constant<int, 3>;
+            using I2 = std::integral_constant<int, 2>;
+            using I1 = std::integral_constant<int, 1>;
+            if (rw == 16 && cw == 1) return rows(I16{}, I1{});
+            if constexpr (sizeof(T) == 8) {
+                if (rw == 8 && cw == 2) return rows(I8{}, I2{});
+                if (rw == 4 && cw == 3) return rows(I4{}, I3{});
+                if (rw == 4 && cw == 5) return rows(I4{}, I5{});
+            } else {
+                if (rw == 16 && cw == 2) return rows(I16{}, I2{});
+                if (rw == 8 && cw == 3) return rows(I8{}, I3{});
+                if (rw == 8 && cw == 5) return rows(I8{}, I5{});
+            }
+        }
         if (S <= 16)
             spline_row<T, MODE, 16><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, outer, R, sp);
         else if (S <= 24 || sizeof(T) == 8)

@@ -51,10 +51,11 @@ def test_adjoint_sweeps_and_shift_derivatives(method, dt):
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-@pytest.mark.parametrize("n", [100, 150, 257])
+@pytest.mark.parametrize("n", [100, 150, 192, 257])
 def test_spline_shift_derivative_long_contiguous_rows(dt, n):
-    # rows of the contiguous axis longer than one and two wavefronts (the
-    # unrolled column blocks and the loop after them), a ragged last tile
+    # rows of the contiguous axis longer than one and two wavefronts, a
+    # ragged last tile; the shift derivative by rows (100, 192 and 257
+    # points) and by segments (150)
     vp = require_gpu()
     dims = (3, 4, 5, n)
     u = random_field(dims, seed=11)
