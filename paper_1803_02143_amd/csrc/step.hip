@@ -72,8 +72,10 @@ hipEvent_t take_event(vp_state* st) {
         st->free_events.pop_back();
         return e;
     }
+    // timing only: no system-scope fence (cache writeback and invalidate)
+    // at each record, which would cost the launches between the events time
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
