@@ -351,6 +351,14 @@ enum {
     VP_TIMER_COUNT = 7
 };
 VP4D_API vp_status vp_timing_enable(vp_state* st, int enable);
+/*
+ * vp_timing_select -- time only the categories whose bit (1 << VP_TIMER_x) is
+ * set in `mask` (0: none; vp_timing_enable(st, 1) selects all).  Each timed
+ * launch costs two event records on the stream, so a caller that needs one
+ * category's durations selects only that one.  Bits at or above
+ * VP_TIMER_COUNT are VP_ERR_ARG.
+ */
+VP4D_API vp_status vp_timing_select(vp_state* st, unsigned mask);
 VP4D_API vp_status vp_timing_read(vp_state* st, double* ms, int64_t* counts);
 
 /*

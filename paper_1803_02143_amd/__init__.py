@@ -333,6 +333,15 @@ class VPState:
     def timing_enable(self, on=True):
         _check("vp_timing_enable", lib().vp_timing_enable(self._h, 1 if on else 0))
 
+    def timing_select(self, names):
+        """Time only the named categories (keys of ``timing_read``)."""
+        mask = 0
+        for n in names:
+            if n not in TIMER_NAMES:
+                raise ValueError(f"unknown timer {n!r}; known: {TIMER_NAMES}")
+            mask |= 1 << TIMER_NAMES.index(n)
+        _check("vp_timing_select", lib().vp_timing_select(self._h, mask))
+
     def timing_read(self):
         """{timer name: (total ms, launches)} since the last read."""
         ms = (ctypes.c_double * _lib.VP_TIMER_COUNT)()

@@ -83,6 +83,7 @@ SIGNATURES = {
     "vp_strang_adjoint": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, ctypes.c_size_t,
                                          _vp]),
     "vp_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "vp_timing_select": (ctypes.c_int, [_vp, ctypes.c_uint]),
     "vp_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int64)]),
     "vp_copy_pattern": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64x4, ctypes.c_int, _vp,

@@ -50,7 +50,7 @@ struct vp_state {
     double* rho_part_d;
     double *rho_d, *e1_d, *e2_d;
     void* pws_d;
-    bool timing;
+    unsigned timing;   // bit t: timer category t records its launches
     std::vector<hipEvent_t> ev[VP_TIMER_COUNT];  // start/stop pairs
     std::vector<hipEvent_t> free_events;
 };
@@ -80,7 +80,7 @@ hipEvent_t take_event(vp_state* st) {
 }
 
 void mark(vp_state* st, int timer, hipStream_t s) {
-    if (!st->timing) return;
+    if (!(st->timing >> timer & 1u)) return;
     hipEvent_t e = take_event(st);
     if (!e) return;
     (void)hipEventRecord(e, s);
@@ -340,7 +340,7 @@ extern "C" vp_status vp_create(vp_state** out, int method, int degree, vp_dtype 
         delete st;
         return set_error(VP_ERR_HIP, "stream or event creation failed: %s", hipGetErrorString(e));
     }
-    st->timing = false;
+    st->timing = 0;
     *out = st;
     return VP_OK;
 }
@@ -496,7 +496,17 @@ extern "C" vp_status vp_strang_run(vp_state* st, void* f, void* f_tmp, int nstep
 extern "C" vp_status vp_timing_enable(vp_state* st, int enable) {
     clear_error();
     if (!st) return set_error(VP_ERR_ARG, "st is NULL");
-    st->timing = enable != 0;
+    st->timing = enable != 0 ? (1u << VP_TIMER_COUNT) - 1u : 0u;
+    return VP_OK;
+}
+
+extern "C" vp_status vp_timing_select(vp_state* st, unsigned mask) {
+    clear_error();
+    if (!st) return set_error(VP_ERR_ARG, "st is NULL");
+    if (mask >> VP_TIMER_COUNT)
+        return set_error(VP_ERR_ARG, "timer mask 0x%x has bits beyond the %d categories", mask,
+                         static_cast<int>(VP_TIMER_COUNT));
+    st->timing = mask;
     return VP_OK;
 }
 

@@ -127,6 +127,7 @@ def test_adjoint_and_run_argument_errors():
     assert lib.vp_strang_adjoint(None, pa, pb, 0.1, pg, 1 << 20, None) == L.VP_ERR_ARG
     assert lib.vp_energy_gradient(None, pa, pb, None, None) == L.VP_ERR_ARG
     assert lib.vp_strang_run(None, pa, pb, 4, 0.1, 2, None, None, None) == L.VP_ERR_ARG
+    assert lib.vp_timing_select(None, 1) == L.VP_ERR_ARG
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

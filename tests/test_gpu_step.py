@@ -409,12 +409,22 @@ def test_step_parity_with_density_from_the_x2_sweep(method, dt, dims):
     tol = 1e-12 if dt == "f64" else 1e-5
     assert np.max(np.abs(to_host(W) - Wr) / Wr) <= tol
     np.testing.assert_allclose(to_host(mom).reshape(3, 4), mr, rtol=tol)
-    # the same steps with W only (density without the moment sums)
+    # the same steps with W only (density without the moment sums), timing
+    # only the x1 sweeps: the other categories record nothing
     fd2 = to_dev(f_in, dt)
     W2 = torch.empty(3, dtype=torch.float64, device="cuda")
+    st.timing_select(["sweep_x1"])
     st.step(fd2, tmp, 2, w.dt, W2)
+    timers = st.timing_read()
+    st.timing_enable(False)
+    assert timers["sweep_x1"][1] == 4, timers
+    assert all(c == 0 for k, (_, c) in timers.items() if k != "sweep_x1"), timers
     assert torch.equal(fd2, fd)
     assert np.max(np.abs(to_host(W2) - Wr) / Wr) <= tol
+    with pytest.raises(ValueError):
+        st.timing_select(["sweep_x3"])
+    from paper_1803_02143_amd import _lib as L
+    assert vp.lib().vp_timing_select(st._h, 1 << L.VP_TIMER_COUNT) == L.VP_ERR_ARG
     st.close()
 
 
