@@ -969,9 +969,11 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
         const int Q = kBlock / R;
         const int S = (n + Q - 1) / Q;
         if constexpr (MODE == kDshift) {
-            // by rows where the wavefront's share of lam fits 16-24 FP64 or
-            // 16-40 FP32 registers: rows per wavefront and 64-point chunks
-            // per row (rows of up to 64, 128, 192 and 320 points)
+            // by rows where a lane's share of lam is 12-20 FP64 or 16-40
+            // FP32 values: rows per wavefront and 64-point chunks per row
+            // (rows of at most 64, 96-128, 192 and 257-320 points in FP64;
+            // at most 128, 192 and 257-320 in FP32); other lengths by
+            // segments
             const int rw = R / (kBlock / 64), cw = (n + 63) / 64;
             auto rows = [&](auto rwc, auto cwc) {
                 spline_row<T, MODE, 1, decltype(rwc)::value, decltype(cwc)::value>
