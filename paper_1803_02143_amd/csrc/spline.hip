@@ -18,7 +18,8 @@
 //
 // Tiles: lines along a strided axis are staged as [n][L] (L adjacent lines,
 // one per lane, contiguous along the fastest axis); lines along the
-// contiguous axis as [R][n+1] (padded against LDS bank conflicts).  One
+// contiguous axis as [R][n+3] (an odd row length for even n, against LDS
+// bank conflicts; room for wrapped copies of a row's first points).  One
 // thread per line runs the two recursions; all threads load, evaluate and
 // store element-parallel with contiguous global accesses.
 #include <algorithm>
@@ -529,14 +530,18 @@ spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
 // (RW of them) and lane l points l, l + 64, ... (CW of them), so that lam
 // arrives by whole-row loads.
 template <typename T, int MODE, int LS, int RW = 0, int CW = 0>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LS == 16 || RW > 0 ? 6 : 1)))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
+    LS == 16 || (RW > 0 && RW <= 8 && RW * CW * sizeof(T) <= 128) ? 6 : RW > 0 ? 5 : 1)))
 spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ lam,
            double* __restrict__ g, const double* __restrict__ shift, ShiftMap sm,
            int64_t nrows, int R, SplineParams<T> sp) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = sp.n;
-    const int ld = n + 1;
-    T* buf = reinterpret_cast<T*>(smem);   // [R][n+1]
+    // rows padded by three: after the solve, the rows read by four-tap
+    // windows get wrapped copies of their first three points there, so that
+    // the taps of any point are consecutive
+    const int ld = n + 3;
+    T* buf = reinterpret_cast<T*>(smem);   // [R][n+3]
     T* wts = buf + R * ld;                 // [R][4]
     int* sh = reinterpret_cast<int*>(wts + 4 * R);
 
@@ -643,6 +648,17 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                                active);
         spline_solve_segment<T>(buf + r * ld, 1, b, e, active, sp);
     }
+    // the evaluations by rows (FP64 forward, shift derivative by rows) read
+    // windows row[j0 .. j0 + 3], j0 in [0, n): point n + k holds point k mod n
+    constexpr bool kPadded = (MODE == kFwd && sizeof(T) == 8) || (MODE == kDshift && RW > 0);
+    if constexpr (kPadded) {
+        for (int t = threadIdx.x; t < 3 * nr; t += kBlock) {
+            const int r = t / 3;
+            const int k = t - 3 * r;
+            buf[r * ld + n + k] = buf[r * ld + (k < n ? k : k % n)];
+        }
+        __syncthreads();
+    }
     if (MODE == kFwd && sizeof(T) == 4) {
         // FP32: each thread evaluates its own segment (the solve's mapping)
         // with a sliding window over the row, one LDS read per output, and
@@ -718,9 +734,8 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
             const T w2 = wts[4 * r + 2], w3 = wts[4 * r + 3];
             const int s = sh[r];
             for (int i = lane; i < n; i += 64) {
-                const int j0 = first_tap(i, s, n);
-                const int j1 = next_idx(j0, n), j2 = next_idx(j1, n), j3 = next_idx(j2, n);
-                put_out(&dst[i], fma(w3, row[j3], fma(w2, row[j2], fma(w1, row[j1], w0 * row[j0]))));
+                const T* c = row + first_tap(i, s, n);
+                put_out(&dst[i], fma(w3, c[3], fma(w2, c[2], fma(w1, c[1], w0 * c[0]))));
             }
         }
         return;
@@ -769,9 +784,8 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                     for (int m = 0; m < CW; ++m) {
                         const int i = lane + 64 * m;
                         if (i < n) {
-                            const int j0 = first_tap(i, s, n);
-                            const int j1 = next_idx(j0, n), j2 = next_idx(j1, n), j3 = next_idx(j2, n);
-                            const T v = fma(w3, row[j3], fma(w2, row[j2], fma(w1, row[j1], w0 * row[j0])));
+                            const T* c = row + first_tap(i, s, n);
+                            const T v = fma(w3, c[3], fma(w2, c[2], fma(w1, c[1], w0 * c[0])));
                             a[kk] = fma(static_cast<double>(lrow[(k0 + kk) * CW + m]),
                                         static_cast<double>(v), a[kk]);
                         }
@@ -955,7 +969,7 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
                          "spline_advect: line of %d points too long for the LDS tile", n);
     // (the shift derivative adds its segment sums in the tile afterwards:
     // kBlock doubles)
-    const size_t lds = std::max(static_cast<size_t>(R) * (n + 1) * sizeof(T) +
+    const size_t lds = std::max(static_cast<size_t>(R) * (n + 3) * sizeof(T) +
                                     static_cast<size_t>(R) * (4 * sizeof(T) + sizeof(int)),
                                 MODE == kDshift ? kBlock * sizeof(double) : size_t(0));
     const int64_t grid64 = (outer + R - 1) / R;
