@@ -648,10 +648,13 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                                active);
         spline_solve_segment<T>(buf + r * ld, 1, b, e, active, sp);
     }
-    // the evaluations by rows (FP64 forward, shift derivative by rows) read
-    // windows row[j0 .. j0 + 3], j0 in [0, n): point n + k holds point k mod n
-    constexpr bool kPadded = (MODE == kFwd && sizeof(T) == 8) || (MODE == kDshift && RW > 0);
-    if constexpr (kPadded) {
+    // the evaluations that read windows row[j0 .. j0 + 3], j0 in [0, n) (FP64
+    // forward rows, FP32 forward rows of segments over kOV points, the shift
+    // derivative by rows): point n + k holds point k mod n
+    constexpr int kOV = 24;
+    const bool padded = (MODE == kFwd && (sizeof(T) == 8 || (n + kBlock / R - 1) / (kBlock / R) > kOV)) ||
+                        (MODE == kDshift && RW > 0);
+    if (padded) {
         for (int t = threadIdx.x; t < 3 * nr; t += kBlock) {
             const int r = t / 3;
             const int k = t - 3 * r;
@@ -665,7 +668,6 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         // holds the outputs; after a barrier they overwrite the tile, which
         // leaves by flat stores in memory order.  (In FP64 the held outputs
         // would cost the occupancy that the row-by-row evaluation keeps.)
-        constexpr int kOV = 24;
         const int Q = kBlock / R;
         const int S = (n + Q - 1) / Q;
         if (S <= kOV) {
@@ -751,10 +753,9 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
             if (MODE == kAdj) {
                 put_out(&dst[e], row[i]);
             } else {
-                const int j0 = first_tap(i, sh[r], n);
-                const int j1 = next_idx(j0, n), j2 = next_idx(j1, n), j3 = next_idx(j2, n);
+                const T* c = row + first_tap(i, sh[r], n);
                 const T* w = wts + 4 * r;
-                put_out(&dst[e], fma(w[3], row[j3], fma(w[2], row[j2], fma(w[1], row[j1], w[0] * row[j0]))));
+                put_out(&dst[e], fma(w[3], c[3], fma(w[2], c[2], fma(w[1], c[1], w[0] * c[0]))));
             }
             r += dr;
             i += di;
