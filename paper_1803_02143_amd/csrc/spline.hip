@@ -648,80 +648,16 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
                                active);
         spline_solve_segment<T>(buf + r * ld, 1, b, e, active, sp);
     }
-    // the evaluations that read windows row[j0 .. j0 + 3], j0 in [0, n) (FP64
-    // forward rows, FP32 forward rows of segments over kOV points, the shift
-    // derivative by rows): point n + k holds point k mod n
-    constexpr int kOV = 24;
-    const bool padded = (MODE == kFwd && (sizeof(T) == 8 || (n + kBlock / R - 1) / (kBlock / R) > kOV)) ||
-                        (MODE == kDshift && RW > 0);
-    if (padded) {
+    // the evaluations that read windows row[j0 .. j0 + 3], j0 in [0, n) (the
+    // forward rows, the shift derivative by rows): point n + k holds point
+    // k mod n
+    if constexpr (MODE == kFwd || (MODE == kDshift && RW > 0)) {
         for (int t = threadIdx.x; t < 3 * nr; t += kBlock) {
             const int r = t / 3;
             const int k = t - 3 * r;
             buf[r * ld + n + k] = buf[r * ld + (k < n ? k : k % n)];
         }
         __syncthreads();
-    }
-    if (MODE == kFwd && sizeof(T) == 4) {
-        // FP32: each thread evaluates its own segment (the solve's mapping)
-        // with a sliding window over the row, one LDS read per output, and
-        // holds the outputs; after a barrier they overwrite the tile, which
-        // leaves by flat stores in memory order.  (In FP64 the held outputs
-        // would cost the occupancy that the row-by-row evaluation keeps.)
-        const int Q = kBlock / R;
-        const int S = (n + Q - 1) / Q;
-        if (S <= kOV) {
-            const int r = threadIdx.x % R;
-            const int b = min(n, (static_cast<int>(threadIdx.x) / R) * S);
-            const int e = min(n, b + S);
-            const bool active = r < nr && b < e;
-            T ov[kOV];
-            if (active) {
-                const T* row = buf + r * ld;
-                const T w0 = wts[4 * r + 0], w1 = wts[4 * r + 1];
-                const T w2 = wts[4 * r + 2], w3 = wts[4 * r + 3];
-                int j = first_tap(b, sh[r], n);
-                T c0 = row[j];
-                j = next_idx(j, n);
-                T c1 = row[j];
-                j = next_idx(j, n);
-                T c2 = row[j];
-                j = next_idx(j, n);
-                T c3 = row[j];
-#pragma unroll
-                for (int t = 0; t < kOV; ++t) {
-                    if (b + t < e) {
-                        ov[t] = fma(w3, c3, fma(w2, c2, fma(w1, c1, w0 * c0)));
-                        c0 = c1;
-                        c1 = c2;
-                        c2 = c3;
-                        j = next_idx(j, n);
-                        c3 = row[j];
-                    }
-                }
-            }
-            __syncthreads();
-            if (active) {
-                T* row = buf + r * ld;
-#pragma unroll
-                for (int t = 0; t < kOV; ++t)
-                    if (b + t < e) row[b + t] = ov[t];
-            }
-            __syncthreads();
-            T* __restrict__ dst = fout + row0 * n;
-            int rr = static_cast<int>(threadIdx.x) / n;
-            int i = static_cast<int>(threadIdx.x) - rr * n;
-            for (int f = threadIdx.x; f < cnt; f += kBlock) {
-                put_out(&dst[f], buf[rr * ld + i]);
-                rr += dr;
-                i += di;
-                if (i >= n) {
-                    i -= n;
-                    ++rr;
-                }
-            }
-            return;
-        }
     }
     if (MODE != kDshift && sizeof(T) == 8) {
         // FP64: row by row, the row's weights and shift held in registers
@@ -743,8 +679,9 @@ spline_row(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict_
         return;
     }
     if (MODE != kDshift) {
-        // FP32 transposed rows, and forward rows of segments over 24 points:
-        // flat stores in memory order (no idle lanes at row ends)
+        // FP32 rows, forward and transposed: element-parallel in memory
+        // order (no idle lanes at row ends), the forward taps read as
+        // windows of the padded row
         T* __restrict__ dst = fout + row0 * n;
         int r = static_cast<int>(threadIdx.x) / n;
         int i = static_cast<int>(threadIdx.x) - r * n;

@@ -132,9 +132,9 @@ def test_sldg_mass_conserved_to_roundoff():
         assert np.max(np.abs(m1 - m0)) <= 1e-13 * np.max(np.abs(m0))
 
 
-# (contiguous rows of 96 and 130 points: the row-tile segment lengths on
-# both sides of the FP32 register-held evaluation; strided lines of 80
-# points: FP64 column segments over 16 points)
+# (contiguous rows of 1, 3, 16, 67, 96 and 130 points: the padded row
+# windows with wrapped copies shorter and longer than the row; strided lines
+# of 80 points: FP64 column segments over 16 points)
 SPLINE_DIMS = [(12, 10, 9, 16), (7, 24, 5, 3), (3, 5, 40, 6), (4, 3, 6, 67), (2, 2, 2, 1),
                (3, 2, 5, 96), (2, 3, 4, 130), (3, 80, 5, 4)]
 
