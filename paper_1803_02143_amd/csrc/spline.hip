@@ -285,12 +285,15 @@ __device__ __forceinline__ void transposed_taps(T* p, int stride, int b, int e, 
 //   kAdj:    fout = C^{-1} E(alpha)^T fin            (fin = adjoint of the output)
 //   kDshift: g[line] = <lam, E'(alpha) C^{-1} fin>    (per-line shift derivative)
 // LS bounds the thread's segment: the FP64 loads in flight, the shift
-// derivative's lam and the transposed taps take that many registers.
-template <typename T, int AXIS, int MODE, int LS = SegMax<T>::value>
+// derivative's lam and the transposed taps take that many registers.  LT > 0
+// fixes the tile's line count L at compile time (64-line tiles): the solve's
+// strided LDS accesses then pair into stride-64 two-address loads and stores.
+template <typename T, int AXIS, int MODE, int LS = SegMax<T>::value, int LT = 0>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LS == 16 ? 5 : 1)))
 spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ lam,
            double* __restrict__ g, const double* __restrict__ shift, ShiftMap sm,
-           int64_t nlines, int64_t inner, int L, SplineParams<T> sp, RhoFuse rf) {
+           int64_t nlines, int64_t inner, int L_, SplineParams<T> sp, RhoFuse rf) {
+    const int L = LT > 0 ? LT : L_;
     constexpr bool RHO = MODE == kFwdRho || MODE == kFwdRhoMom;
     constexpr bool MOM = MODE == kFwdRhoMom;
     constexpr bool FWD = MODE == kFwd || RHO;
@@ -846,9 +849,10 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
             static std::atomic<bool> attr_set{false};
             if (!attr_set.load(std::memory_order_relaxed)) {
                 // dynamic LDS beyond the default (one setting covers the axes)
-                const void* fns[3] = {reinterpret_cast<const void*>(&spline_col<T, 0, MODE>),
-                                      reinterpret_cast<const void*>(&spline_col<T, 1, MODE>),
-                                      reinterpret_cast<const void*>(&spline_col<T, 2, MODE>)};
+                // (only the fused x2 sweeps take tiles over 48 KiB)
+                const void* fns[2] = {
+                    reinterpret_cast<const void*>(&spline_col<T, 1, MODE>),
+                    reinterpret_cast<const void*>(&spline_col<T, 1, MODE, SegMax<T>::value, 64>)};
                 for (const void* fn : fns)
                     VP_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                    static_cast<int>(kFwdTileBytes)));
@@ -861,21 +865,32 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
             return set_error(VP_ERR_UNSUPPORTED, "spline_advect: grid too large");
         const unsigned grid = static_cast<unsigned>(grid64);
         if constexpr (MODE == kFwdRho || MODE == kFwdRhoMom) {
-            spline_col<T, 1, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
+            if (L == 64)
+                spline_col<T, 1, MODE, SegMax<T>::value, 64><<<grid, kBlock, lds, st>>>(
+                    in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
+            else
+                spline_col<T, 1, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
         } else {
             auto go = [&](auto ls) {
                 constexpr int LS = decltype(ls)::value;
-                switch (axis) {
-                    case 0:
-                        spline_col<T, 0, MODE, LS><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
-                        break;
-                    case 1:
-                        spline_col<T, 1, MODE, LS><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
-                        break;
-                    default:
-                        spline_col<T, 2, MODE, LS><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
-                        break;
-                }
+                auto launch = [&](auto lt) {
+                    constexpr int LT = decltype(lt)::value;
+                    switch (axis) {
+                        case 0:
+                            spline_col<T, 0, MODE, LS, LT><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
+                            break;
+                        case 1:
+                            spline_col<T, 1, MODE, LS, LT><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
+                            break;
+                        default:
+                            spline_col<T, 2, MODE, LS, LT><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
+                            break;
+                    }
+                };
+                if (L == 64)
+                    launch(std::integral_constant<int, 64>{});
+                else
+                    launch(std::integral_constant<int, 0>{});
             };
             // segment of ceil(n / (kBlock / L)) points: 16 or 24 registers
             // where it fits (FP32 forward loads go in batches of 12 and take
