@@ -286,8 +286,10 @@ __device__ __forceinline__ void transposed_taps(T* p, int stride, int b, int e, 
 //   kDshift: g[line] = <lam, E'(alpha) C^{-1} fin>    (per-line shift derivative)
 // LS bounds the thread's segment: the FP64 loads in flight, the shift
 // derivative's lam and the transposed taps take that many registers.  LT > 0
-// fixes the tile's line count L at compile time (64-line tiles): the solve's
-// strided LDS accesses then pair into stride-64 two-address loads and stores.
+// fixes the tile's line count L at compile time (64-line tiles, and FP64
+// 32-line ones): the solve's strided LDS accesses then pair into two-address
+// loads and stores.  (FP32 32-line tiles ran slower that way: the 288^4 x1
+// sweep 12.5 against 11.4 ms.)
 template <typename T, int AXIS, int MODE, int LS = SegMax<T>::value, int LT = 0>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LS == 16 ? 5 : 1)))
 spline_col(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ lam,
@@ -850,9 +852,10 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
             if (!attr_set.load(std::memory_order_relaxed)) {
                 // dynamic LDS beyond the default (one setting covers the axes)
                 // (only the fused x2 sweeps take tiles over 48 KiB)
-                const void* fns[2] = {
+                const void* fns[3] = {
                     reinterpret_cast<const void*>(&spline_col<T, 1, MODE>),
-                    reinterpret_cast<const void*>(&spline_col<T, 1, MODE, SegMax<T>::value, 64>)};
+                    reinterpret_cast<const void*>(&spline_col<T, 1, MODE, SegMax<T>::value, 64>),
+                    reinterpret_cast<const void*>(&spline_col<T, 1, MODE, SegMax<T>::value, 32>)};
                 for (const void* fn : fns)
                     VP_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                    static_cast<int>(kFwdTileBytes)));
@@ -867,6 +870,9 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
         if constexpr (MODE == kFwdRho || MODE == kFwdRhoMom) {
             if (L == 64)
                 spline_col<T, 1, MODE, SegMax<T>::value, 64><<<grid, kBlock, lds, st>>>(
+                    in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
+            else if (L == 32 && sizeof(T) == 8)
+                spline_col<T, 1, MODE, SegMax<T>::value, 32><<<grid, kBlock, lds, st>>>(
                     in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
             else
                 spline_col<T, 1, MODE><<<grid, kBlock, lds, st>>>(in, out, lm, g, shift, sm, nlines, inner, L, sp, rf);
@@ -889,6 +895,8 @@ vp_status launch_spline(int axis, const int64_t dims[4], const void* fin,
                 };
                 if (L == 64)
                     launch(std::integral_constant<int, 64>{});
+                else if (L == 32 && sizeof(T) == 8)
+                    launch(std::integral_constant<int, 32>{});
                 else
                     launch(std::integral_constant<int, 0>{});
             };

@@ -134,9 +134,10 @@ def test_sldg_mass_conserved_to_roundoff():
 
 # (contiguous rows of 1, 3, 16, 67, 96 and 130 points: the padded row
 # windows with wrapped copies shorter and longer than the row; strided lines
-# of 80 points: FP64 column segments over 16 points)
+# of 80 points: FP64 column segments over 16 points; of 130 and 200 points:
+# 32-line column tiles in FP64 and FP32, 16-line ones in FP64)
 SPLINE_DIMS = [(12, 10, 9, 16), (7, 24, 5, 3), (3, 5, 40, 6), (4, 3, 6, 67), (2, 2, 2, 1),
-               (3, 2, 5, 96), (2, 3, 4, 130), (3, 80, 5, 4)]
+               (3, 2, 5, 96), (2, 3, 4, 130), (3, 80, 5, 4), (3, 130, 4, 5), (2, 200, 3, 4)]
 
 
 @pytest.mark.parametrize("dims", SPLINE_DIMS)
