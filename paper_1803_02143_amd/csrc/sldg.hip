@@ -926,14 +926,16 @@ vp_status launch_sldg_rho_j(const int64_t dims[4], const void* fin, void* fout,
 // and velocity columns per thread.
 constexpr int kRhoSegJ32 = 2;   // FP32: columns per thread
 constexpr int kRhoSegC32 = 8;   // FP32: cells per segment
+// (degree 3 by whole lines: its row-segment form held 233-237 registers, two
+// wavefronts a SIMD, and took 1010 against 820 us at 128^4)
 constexpr int rho_seg_cells(int M, bool f32) {
-    return M > 4 ? 0 : (M == 4 ? kSegCells / 2 : (f32 ? kRhoSegC32 : kSegCells));
+    return M > 3 ? 0 : (f32 ? kRhoSegC32 : kSegCells);
 }
 constexpr int rho_seg_cols(int M, bool f32) { return f32 && M <= 3 ? kRhoSegJ32 : 1; }
 
 // The fused x2 sweep runs by row segments where its band blocks apply:
 // N3 N4 / J a multiple of 256, x2 rows of at most 16 MB, an x1 plane under
-// 4 GB and degree <= 3; otherwise one thread per whole line (`sldg_col_rho`).
+// 4 GB and degree <= 2; otherwise one thread per whole line (`sldg_col_rho`).
 int rho_seg_stack(vp_dtype dt, int degree, const int64_t dims[4]) {
     const int64_t inner = dims[2] * dims[3];
     const size_t es = dtype_size(dt);
@@ -969,7 +971,7 @@ vp_status launch_sldg_rho_seg(const int64_t dims[4], const void* fin, void* fout
                 static_cast<const T*>(fin), static_cast<T*>(fout), shift, sm, nc, inner, nseg, b, rf);
         return check_launch("sldg_seg_rho");
     }
-    return set_error(VP_ERR_UNSUPPORTED, "fused x2 sweep by segments: degree <= 3");
+    return set_error(VP_ERR_UNSUPPORTED, "fused x2 sweep by segments: degree <= 2");
 }
 
 template <int M, typename T>
